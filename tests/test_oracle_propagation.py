@@ -1,0 +1,174 @@
+"""Pins of the oracle's time propagation against closed forms and invariants (Sec. 5 and 6)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from workloads import config
+from oracle.stepper import Propagator
+from tests.oracle_dense import dense_parts
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_one_step_matches_dense_exponential():
+    """A linear step equals exp(dt A) wbar with A built from the assembled B^T D B stiffness."""
+    p = config("c1")
+    rng = np.random.default_rng(1)
+    pr = Propagator(p)
+    N = pr.N
+    u0 = pr.full(rng.normal(0, 1e-6, N)); v0 = pr.full(rng.normal(0, 1e-3, N))
+    p = p.with_(u0=u0, v0=v0)
+    Hb, Pb, Mh, free, _ = dense_parts(p)
+    A = np.zeros((2 * N + 1, 2 * N + 1))
+    A[:N, N:2 * N] = np.eye(N); A[N:2 * N, :N] = -Hb; A[N:2 * N, 2 * N] = Pb
+    pr = Propagator(p)
+    w0 = np.concatenate([pr.ubar, pr.vbar, [1.0]])
+    pr.step(p.dt)
+    ref = sla.expm(p.dt * A) @ w0
+    got = np.concatenate([pr.ubar, pr.vbar, [1.0]])
+    assert np.linalg.norm(got - ref) <= 20 * p.tol * np.linalg.norm(w0)
+
+
+def test_linear_closed_form_with_constant_load():
+    """ubar(t) = us + cos(sqrt(Hbar) t)(ubar0 - us) + sqrt(Hbar)^-1 sin(sqrt(Hbar) t) vbar0 (Sec. 5.2)."""
+    p = config("c1", n_steps=100, tol=1e-12)
+    Hb, Pb, Mh, free, pr = dense_parts(p)
+    lam, Q = np.linalg.eigh(Hb)
+    om = np.sqrt(lam)
+    us = Q @ ((Q.T @ Pb) / lam)
+    pr.run(p.dt, p.n_steps)
+    t = p.dt * p.n_steps
+    a = Q.T @ (0.0 - us)
+    u_ex = us + Q @ (np.cos(om * t) * a)
+    v_ex = Q @ (-om * np.sin(om * t) * a)
+    # accumulated Krylov error of 100 steps at tol 1e-12 (round-off floor ~1e-9)
+    assert _rel(pr.ubar, u_ex) < 3e-9
+    assert _rel(pr.vbar, v_ex) < 1e-8
+
+
+def test_linear_error_is_flat_in_dt():
+    """Linear elastodynamics has no Magnus truncation error (Sec. 5.1): the error against
+    the closed form does not grow with dt (superquadratic in the paper's wording)."""
+    p = config("c1", tol=1e-12)
+    Hb, Pb, Mh, free, _ = dense_parts(p)
+    lam, Q = np.linalg.eigh(Hb)
+    om = np.sqrt(lam)
+    us = Q @ ((Q.T @ Pb) / lam)
+    T = 4e-3
+    errs = []
+    for dt in (2e-4, 4e-4, 1e-3):
+        pr = Propagator(p, m_max=200)
+        pr.run(dt, int(round(T / dt)))
+        u_ex = us + Q @ (np.cos(om * T) * (Q.T @ (-us)))
+        errs.append(_rel(pr.ubar, u_ex))
+    # omega_max * dt reaches ~200 here: any O(dt^2) truncation error would be O(1).  What is
+    # left is Krylov error and round-off (which grows mildly with the subspace size m).
+    assert max(errs) < 3e-8
+
+
+def _bar_modes(n, k, t, h, E, rho):
+    c = np.sqrt(E / rho)
+    om = 2 * c / h * np.sin((2 * k - 1) * np.pi / (4 * n))
+    j = np.arange(n + 1)
+    phi = np.sin((2 * k - 1) * np.pi * j / (2 * n))
+    return phi, om
+
+
+def test_1d_bar_closed_form():
+    """nx x 1 x 1 hex8 bar with all y/z DOFs and x = 0 clamped is exactly the 1D lumped
+    chain with modulus lambda + 2 mu: modes sin((2k-1) pi j / 2n), frequencies
+    (2c/h) sin((2k-1) pi / 4n) (derivation recorded with the workload)."""
+    nx, h = 16, 0.0625
+    p = config("bar", nx=nx, h=h, dt=2e-5, n_steps=8)
+    lam = 200e9 * 0.3 / (1.3 * 0.4); mu = 200e9 / 2.6
+    E1 = lam + 2 * mu
+    xi = np.rint(p.xyz[:, 0] / h).astype(int)
+    u0 = np.zeros(3 * p.n_nodes); v0 = np.zeros(3 * p.n_nodes)
+    amps = {1: (1e-4, 0.3), 2: (-3e-5, 0.0), 5: (0.0, -0.05)}
+    for k, (a, b) in amps.items():
+        phi, om = _bar_modes(nx, k, 0.0, h, E1, 7800.0)
+        u0[0::3] += a * phi[xi]
+        v0[0::3] += b * phi[xi]
+    p = p.with_(u0=u0, v0=v0)
+    pr = Propagator(p, tol=1e-13)
+    pr.run(p.dt, p.n_steps)
+    t = p.dt * p.n_steps
+    u_ex = np.zeros_like(u0); v_ex = np.zeros_like(v0)
+    for k, (a, b) in amps.items():
+        phi, om = _bar_modes(nx, k, t, h, E1, 7800.0)
+        u_ex[0::3] += (a * np.cos(om * t) + b / om * np.sin(om * t)) * phi[xi]
+        v_ex[0::3] += (-a * om * np.sin(om * t) + b * np.cos(om * t)) * phi[xi]
+    assert _rel(pr.u(), u_ex) < 1e-9
+    assert _rel(pr.v(), v_ex) < 1e-9
+
+
+def test_energy_conserved_without_load():
+    """E_n = E_0 for linear elastodynamics with Pbar = 0 (Sec. 5.2)."""
+    p = config("c1", n_steps=50)
+    n3 = 3 * p.n_nodes
+    rng = np.random.default_rng(3)
+    pr0 = Propagator(p)
+    v0 = pr0.full(rng.normal(0, 1e-2, pr0.N))
+    p = p.with_(t0=np.zeros(3), v0=v0)
+    pr = Propagator(p)
+    e0 = sum(pr.energies()[:2])
+    drift = []
+    for _ in range(p.n_steps):
+        pr.step(p.dt)
+        ke, se, we = pr.energies()
+        drift.append(abs(ke + se - e0) / e0)
+    assert max(drift) < 10 * p.n_steps * p.tol
+
+
+def test_one_step_map_is_symplectic():
+    """Phi^T J Phi = J for the one-step map (Sec. 5.3), built column by column."""
+    p = config("c1", nx=3, ny=1, nz=1)
+    p = p.with_(t0=np.zeros(3))
+    pr = Propagator(p, tol=1e-14)
+    N = pr.N
+    Phi = np.zeros((2 * N, 2 * N))
+    for c in range(2 * N):
+        e = np.zeros(2 * N + 1); e[c] = 1.0; e[2 * N] = 0.0
+        y, _ = pr.propagate(e, 1e-4, 0.0, None, "corr")
+        Phi[:, c] = y[:2 * N]
+    J = np.block([[np.zeros((N, N)), np.eye(N)], [-np.eye(N), np.zeros((N, N))]])
+    assert np.abs(Phi.T @ J @ Phi - J).max() < 1e-9 * np.abs(Phi).max() ** 2
+
+
+def _nh_bar(dt, T, load=4e4):
+    p = config("c3", nx=6, ny=1, nz=1, dt=dt, n_steps=int(round(T / dt)))
+    return p.with_(t0=np.array([0.0, 0.0, -load]), knots_t=np.array([0.0, 0.004]),
+                   knots_s=np.array([0.0, 1.0]))
+
+
+@pytest.mark.slow
+def test_nonlinear_second_order_in_dt():
+    """Sec. 5.1: the truncated Magnus propagator with the predictor-corrector is second order."""
+    T = 0.008
+    ref = Propagator(_nh_bar(T / 256, T), tol=1e-13, m_max=64)
+    ref.run(T / 256, 256)
+    errs = []
+    for n in (8, 16, 32):
+        pr = Propagator(_nh_bar(T / n, T), tol=1e-13, m_max=64)
+        pr.run(T / n, n)
+        errs.append(_rel(pr.u(), ref.u()))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 1.7) & (orders < 2.4)), (errs, orders)
+
+
+def test_small_load_limit_is_linear():
+    """As the load tends to zero the Neo-Hookean trajectory approaches the linear one."""
+    diffs = []
+    for load in (1e3, 1e2):
+        pn = config("c3", nx=6, ny=1, nz=1, dt=5e-4, n_steps=6)
+        pn = pn.with_(t0=np.array([0.0, 0.0, -load]), knots_t=np.array([0.0]), knots_s=np.array([1.0]))
+        lam, mu = 2.0e6, 0.4e6
+        E = mu * (3 * lam + 2 * mu) / (lam + mu); nu = lam / (2 * (lam + mu))
+        pl = pn.with_(model="linear", params=(E, nu))
+        a = Propagator(pn); a.run(pn.dt, pn.n_steps)
+        b = Propagator(pl); b.run(pl.dt, pl.n_steps)
+        diffs.append(_rel(a.u(), b.u()))
+    assert diffs[1] < diffs[0] / 5.0
+    assert diffs[1] < 1e-3
