@@ -1,0 +1,226 @@
+/*
+ * ep.h -- C ABI of the MI355X (gfx950) exponential time propagator for elastodynamics.
+ *
+ * Method: Pari, Kanungo & Gavini, "Exponential time propagators for elastodynamics".
+ *   The finite-element semi-discrete system M u'' + H(u) u = P(t) (Sec. 2.2-2.3) is
+ *   rewritten with ubar = M^{1/2} u as d/dt wbar = A wbar, wbar = [ubar; vbar; s],
+ *   A = [[0, I, 0], [-M^{-1/2} H M^{-1/2}, 0, M^{-1/2} P / s0], [0, 0, 0]] (Sec. 2.3),
+ *   advanced by wbar_n = exp(dt A(t_{n-1} + dt/2)) wbar_{n-1} (first Magnus term and the
+ *   midpoint rule, Sec. 3.3 and 4.1) with a predictor-corrector for the nonlinear
+ *   H at the midpoint (Sec. 4.2).  exp(dt A) wbar is evaluated by Arnoldi (modified
+ *   Gram-Schmidt) with the subspace error estimate choosing the subspace size and
+ *   exp(H_m) by Taylor / scaling-and-squaring Pade (Sec. 4.3).
+ *
+ * Discretisation: 8-node hexahedra (VTK node order), 2x2x2 Gauss quadrature for the
+ *   internal force, vertex (2-point Gauss-Lobatto) rule for a diagonal mass, 2x2 Gauss
+ *   on loaded quad faces.  Nodal vectors are node-major doubles, DOF = 3*node + comp.
+ *
+ * Conventions for every function:
+ *   - returns ep_status: EP_OK (0) or a negative code; never throws or aborts;
+ *   - ep_last_error(ctx) describes the last failure (string owned by ctx, valid until
+ *     the next call on ctx);
+ *   - pointer arguments named *_host are host memory, copied during the call; the
+ *     caller keeps ownership; *_dev arguments are device memory on the context's GPU;
+ *   - a context is not thread-safe; calls on one context must be serialised;
+ *   - device work is enqueued on the context's stream (ep_set_stream) and the calls
+ *     that return data to the host synchronise that stream.
+ */
+#ifndef EP_H
+#define EP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ep_ctx ep_ctx;
+
+typedef enum {
+  EP_OK = 0,
+  EP_ERR_ARG = -1,        /* invalid argument (null pointer, size, range, value)          */
+  EP_ERR_ORDER = -2,      /* call out of order (e.g. step before bind_workspace)          */
+  EP_ERR_HIP = -3,        /* HIP runtime failure (launch, copy, no device)                */
+  EP_ERR_KRYLOV = -4,     /* error estimate above tol at m_max after max_substeps splits  */
+  EP_ERR_INVERTED = -5,   /* det J <= 0: inverted reference element or deformed state     */
+  EP_ERR_NONFINITE = -6,  /* NaN / Inf reached the Krylov recurrence                      */
+  EP_ERR_WORKSPACE = -7,  /* bound workspace too small or misaligned                      */
+  EP_ERR_DEVICE = -8      /* device-side synchronisation timed out (kernel aborted)       */
+} ep_status;
+
+/* Material models and their parameter arrays (App. A of the paper; SI units):
+ *   EP_LINEAR : {E, nu}                      linear elasticity, H = K constant
+ *   EP_NH     : {mu, lambda}                 compressible Neo-Hookean,
+ *               psi = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2
+ *   EP_YEOH   : {C10, C20, C30, D1}          Yeoh, psi = sum_k Ck0 (I1bar - 3)^k + (J-1)^2 / D1;
+ *               C20 = C30 = 0 is the decoupled Neo-Hookean solid (mu = 2 C10, kappa = 2/D1)
+ * For EP_NH and EP_YEOH, H(u) is the secant operator with H(u) u = R(u) exactly,
+ *   (H(u) x)_A = sum_e sum_q w detJ [a (X + G X^T) + (W : X) G] . grad N_A,
+ *   X = grad x, G = F^{-T}, with a, W scalar / matrix coefficients of grad u built as in
+ *   App. A (det F - 1 = P_e : grad u; I1 - 3 = (2 I + grad u) : grad u). */
+typedef enum { EP_LINEAR = 0, EP_NH = 1, EP_YEOH = 2 } ep_model;
+
+/* Arithmetic of the operator apply (stiffness matvec).  The Krylov recurrence, error
+ * estimate, Hessenberg exponential and state are FP64 in every mode.
+ *   EP_PREC_F64       : matvec in FP64
+ *   EP_PREC_MIXED_F32 : element kernels in FP32 with FP32 accumulation; converted at the
+ *                       FP64 Krylov vector boundary. */
+typedef enum { EP_PREC_F64 = 0, EP_PREC_MIXED_F32 = 1 } ep_precision;
+
+/* ------------------------------------------------------------------ lifetime */
+
+/* Create a context on HIP device `hip_device` (>= 0).  hip_device = -1 creates a
+ * host-only context that validates arguments and sizes but can never launch work. */
+ep_status ep_create(ep_ctx** out, int hip_device);
+ep_status ep_destroy(ep_ctx* ctx);
+const char* ep_last_error(const ep_ctx* ctx);
+/* Library version string (static storage). */
+const char* ep_version(void);
+
+/* Stream for all device work (a hipStream_t; NULL = the default stream). */
+ep_status ep_set_stream(ep_ctx* ctx, void* hip_stream);
+
+/* ------------------------------------------------------------------ problem setup
+ * Setup calls must precede ep_bind_workspace; calling one after it returns EP_ERR_ORDER. */
+
+/* Mesh: n_nodes reference coordinates xyz_host[3*n_nodes] (m) and n_elems hex8 cells
+ * conn_host[8*n_elems] (0-based node ids, VTK order).  Sec. 2.2 (finite elements). */
+ep_status ep_set_mesh_hex8(ep_ctx* ctx, int64_t n_nodes, const double* xyz_host,
+                           int64_t n_elems, const int32_t* conn_host);
+
+/* Material (see ep_model) and reference density rho (kg/m^3). */
+ep_status ep_set_material(ep_ctx* ctx, ep_model model, const double* params_host,
+                          int n_params, double rho);
+
+/* Homogeneous Dirichlet DOFs (u = v = 0 for all t): dof ids 3*node + comp.  Duplicates
+ * are allowed.  The clamped DOFs are eliminated from the system (held at zero). */
+ep_status ep_set_dirichlet(ep_ctx* ctx, int64_t n_dofs, const int32_t* dof_ids_host);
+
+/* Dead traction t(t) = scale(t) * t0 on quad faces face_nodes_host[4*n_faces]
+ * (weak-form term 3, Sec. 2.2).  scale(t) is piecewise linear through the n_knots
+ * pairs (t_knots, scale), held constant before the first and after the last knot;
+ * t_knots must be ascending.  n_faces = 0 means no load. */
+ep_status ep_set_traction(ep_ctx* ctx, int64_t n_faces, const int32_t* face_nodes_host,
+                          const double t0_host[3], int64_t n_knots, const double* t_knots_host,
+                          const double* scale_host);
+
+/* Krylov controls (Sec. 4.3).  tol: stop when eps_m <= tol * ||wbar||; m_max: largest
+ * subspace (<= 256); check_every: evaluate eps every this many Arnoldi steps (not
+ * before the size that sufficed on the previous call minus check_every); m_fixed > 0:
+ * exactly m_fixed steps (the paper's fixed-m production mode, Sec. 6.2); k_fixed > 0:
+ * exactly k_fixed substeps; max_substeps: unconverged projections are redone with
+ * 2, 4, ... substeps of the same frozen operator up to this count, then EP_ERR_KRYLOV.
+ * s0: value of the augmented entry of wbar (negative = automatic: 1 with a load, 0
+ * without, which is the paper's 2N form for P = 0). */
+ep_status ep_set_krylov(ep_ctx* ctx, double tol, int m_max, int check_every, int m_fixed,
+                        int k_fixed, int max_substeps, double s0);
+
+ep_status ep_set_precision(ep_ctx* ctx, ep_precision prec);
+
+/* Number of workgroups of the persistent Krylov kernel (0 = automatic / autotuned). */
+ep_status ep_set_launch(ep_ctx* ctx, int workgroups);
+
+/* ------------------------------------------------------------------ workspace
+ * All device memory is caller-owned: query the size, allocate (e.g. a torch uint8
+ * tensor), bind.  The library never allocates or frees device memory itself.
+ * Binding uploads the setup data and runs the setup kernels (geometry, lumped mass,
+ * loads; Sec. 2.2).  The pointer must be 256-byte aligned and stay valid until
+ * ep_destroy.  An inverted reference element gives EP_ERR_INVERTED. */
+ep_status ep_workspace_size(ep_ctx* ctx, size_t* bytes);
+ep_status ep_bind_workspace(ep_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* ------------------------------------------------------------------ state and stepping */
+
+/* Set time t and nodal displacement / velocity (u_host, v_host: 3*n_nodes doubles;
+ * clamped entries are ignored).  Clears the predictor history and the sticky error. */
+ep_status ep_set_state(ep_ctx* ctx, double t, const double* u_host, const double* v_host);
+
+/* Advance n_steps steps of size dt (asynchronous on the stream).  Linear: one
+ * propagation per step; nonlinear: predictor (dt/2) and corrector (dt).  Device-side
+ * failures are sticky and reported by the next synchronising call. */
+ep_status ep_step(ep_ctx* ctx, double dt, int64_t n_steps);
+
+/* Wait for the stream; returns the sticky device error, if any. */
+ep_status ep_sync(ep_ctx* ctx);
+
+/* Synchronising reads.  u_host / v_host: 3*n_nodes doubles (clamped entries 0). */
+ep_status ep_get_state(ep_ctx* ctx, double* t, double* u_host, double* v_host);
+
+/* Energies at the current state (Sec. 5.2 generalised): kinetic 1/2 v^T M v, strain
+ * sum_e sum_q w detJ psi(F), and the work of the current load P(t)^T u. */
+ep_status ep_get_energy(ep_ctx* ctx, double* kinetic, double* strain, double* ext_work);
+
+/* Statistics: total operator applications since ep_set_state, and for the last step
+ * the subspace size and estimate of its last corrector projection, its substep count,
+ * and |s - s0| before the reset of the augmented entry. */
+ep_status ep_get_stats(ep_ctx* ctx, int64_t* matvecs, int* last_m, double* last_eps,
+                       int* last_k, double* aug_drift);
+
+/* Per-step log of the last n steps (n <= 4096): m of the corrector and predictor
+ * projections (first substep), substep counts and eps.  Arrays of length n. */
+ep_status ep_get_step_log(ep_ctx* ctx, int n, int32_t* m_corr, int32_t* m_pred,
+                          int32_t* k_corr, double* eps_corr);
+
+/* ------------------------------------------------------------------ stage entry points
+ * Single stages of the path on device memory of this context's GPU, for checking and
+ * timing.  They use the bound workspace; they do not change the stepping state except
+ * where stated. */
+
+/* y = H(u_lin) x on all 3*n_nodes DOFs (rows and columns of clamped DOFs included;
+ * u_lin = NULL means u = 0, i.e. the linear-elastic stiffness).  x_dev, y_dev, u_lin_dev:
+ * 3*n_nodes doubles.  Weak-form term 2 (Sec. 2.2) with the secant split (App. A). */
+ep_status ep_apply_H(ep_ctx* ctx, const double* u_lin_dev, const double* x_dev, double* y_dev);
+
+/* y = tau * A x with A the augmented first-order matrix (Sec. 2.3) at load scale
+ * `pscale`, u_lin as in ep_apply_H.  x_dev, y_dev: vectors of ep_vector_length() doubles
+ * in the library's layout [ubar (3 n_nodes) | vbar (3 n_nodes) | s | padding]. */
+ep_status ep_apply_A(ep_ctx* ctx, const double* u_lin_dev, double tau, double pscale,
+                     const double* x_dev, double* y_dev);
+ep_status ep_vector_length(ep_ctx* ctx, int64_t* length, int64_t* padded_length);
+
+/* E = exp(H) for a dense m x m row-major matrix (m <= 256) on one workgroup:
+ * Taylor if ||H||_1 <= 1, else scaling and squaring with the [13/13] Pade approximant
+ * (Sec. 4.3).  Host arrays. */
+ep_status ep_expm(ep_ctx* ctx, int m, const double* H_host, double* E_host);
+
+/* m Arnoldi steps with modified Gram-Schmidt (Sec. 4.3) on tau * A (as ep_apply_A) from
+ * w_dev.  Writes V (m+1 rows of padded_length doubles, device) and the Hessenberg
+ * Htilde ((m+1) x m row-major, host).  Returns the number of completed steps in
+ * *steps (< m on breakdown). */
+ep_status ep_arnoldi(ep_ctx* ctx, const double* u_lin_dev, double tau, double pscale,
+                     const double* w_dev, int m, double* V_dev, double* H_host, int* steps);
+
+/* y = exp(tau A) w (one adaptive projection with substeps, Sec. 4.3) on device vectors
+ * of the library layout; reports the subspace size, substeps and estimate. */
+ep_status ep_expv(ep_ctx* ctx, const double* u_lin_dev, double tau, double pscale,
+                  const double* w_dev, double* y_dev, int* m_used, int* k_used, double* eps);
+
+/* ------------------------------------------------------------------ batches
+ * A batch context advances many independent instances (own mesh, material, loads and
+ * state) together: every instance's projections run inside one persistent launch per
+ * step, one workgroup per instance, each with its own subspace size.  Instances are
+ * added after ep_create and before ep_bind_workspace; the single-instance setup calls
+ * are then not used.  The Krylov / precision settings apply to all instances. */
+ep_status ep_batch_add_instance(ep_ctx* ctx, int64_t n_nodes, const double* xyz_host,
+                                int64_t n_elems, const int32_t* conn_host, ep_model model,
+                                const double* params_host, int n_params, double rho,
+                                int64_t n_dirichlet, const int32_t* dof_ids_host,
+                                int64_t n_faces, const int32_t* face_nodes_host,
+                                const double t0_host[3], int64_t n_knots,
+                                const double* t_knots_host, const double* scale_host,
+                                int32_t* instance_id);
+ep_status ep_batch_set_state(ep_ctx* ctx, int32_t instance_id, double t, const double* u_host,
+                             const double* v_host);
+ep_status ep_batch_step(ep_ctx* ctx, double dt, int64_t n_steps);
+ep_status ep_batch_get_state(ep_ctx* ctx, int32_t instance_id, double* t, double* u_host,
+                             double* v_host);
+/* Per-instance statistics of the last step: corrector m and substeps. */
+ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs, int* last_m,
+                             int* last_k, double* last_eps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EP_H */

@@ -1,0 +1,894 @@
+// Host runtime and C ABI of the exponential propagator (see include/ep.h).
+// Owns argument validation, the workspace layout in the caller's device buffer, integer
+// bookkeeping of the mesh (node -> element-slot and node -> face-slot incidence), launch
+// sizing of the persistent kernels and the step sequencing of the predictor-corrector.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ep.h"
+#include "ep_common.hpp"
+#include "ep_kernels.hpp"
+
+using namespace ep;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Layout {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    const size_t o = off;
+    off += bytes;
+    return o;
+  }
+};
+
+// host description + device view of one instance
+struct Inst {
+  // inputs
+  int64_t n_nodes = 0, n_elems = 0;
+  std::vector<double> xyz;
+  std::vector<int32_t> conn;
+  int model = -1;
+  double mp[4] = {0, 0, 0, 0};
+  double rho = 0.0;
+  std::vector<int32_t> clamped;
+  std::vector<int32_t> faces;
+  double t0[3] = {0, 0, 0};
+  std::vector<double> knots;   // times then scales
+  int n_knots = 0;
+  // derived
+  std::vector<int32_t> inc_ptr, inc, finc_ptr, finc;
+  std::vector<unsigned char> clamp_mask;
+  int n3 = 0, L = 0, Lp = 0;
+  // workspace offsets
+  size_t o_xyz, o_conn, o_incp, o_inc, o_geo, o_geo32, o_vdet, o_mih, o_mh, o_p0, o_p0bar, o_faces, o_fincp,
+      o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y,
+      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags;
+  Mesh M{};
+  KWork W{};
+  // stepping state (host mirror)
+  double t = 0.0;
+  int64_t step_idx = 0;
+  int hist_new = -1, hist_old = -1;
+  int nhist = 0;
+  bool state_set = false;
+};
+
+}  // namespace
+
+struct ep_ctx {
+  int device = -1;
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool bound = false;
+  bool batch = false;
+  bool mesh_set = false, material_set = false;
+  Inst one;
+  std::vector<Inst> insts;
+  KrylovCfg cfg{1e-10, 64, 4, 0, 0, 64, 0};
+  double s0_user = -1.0;
+  int G_user = 0;
+  int cus = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t o_batch_tab = 0;
+};
+
+static ep_status fail(ep_ctx* c, ep_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define EP_HIP(c, call)                                                                      \
+  do {                                                                                       \
+    hipError_t _e = (call);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return fail((c), EP_ERR_HIP, std::string(#call " failed: ") + hipGetErrorString(_e));  \
+  } while (0)
+
+static bool is_gpu(const ep_ctx* c) { return c->device >= 0; }
+
+// ------------------------------------------------------------------------------ validation
+static ep_status check_mesh(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn) {
+  if (n_nodes <= 0 || n_elems <= 0) return fail(c, EP_ERR_ARG, "mesh needs n_nodes > 0 and n_elems > 0");
+  if (!xyz || !conn) return fail(c, EP_ERR_ARG, "null mesh array");
+  if (n_nodes > (1LL << 28) || n_elems > (1LL << 27)) return fail(c, EP_ERR_ARG, "mesh too large for 32-bit indexing");
+  for (int64_t i = 0; i < 3 * n_nodes; ++i)
+    if (!std::isfinite(xyz[i])) return fail(c, EP_ERR_ARG, "non-finite node coordinate");
+  for (int64_t i = 0; i < 8 * n_elems; ++i)
+    if (conn[i] < 0 || conn[i] >= n_nodes) return fail(c, EP_ERR_ARG, "connectivity entry out of range");
+  return EP_OK;
+}
+
+static ep_status check_material(ep_ctx* c, int model, const double* p, int n, double rho) {
+  if (!p) return fail(c, EP_ERR_ARG, "null material parameters");
+  if (!(rho > 0.0) || !std::isfinite(rho)) return fail(c, EP_ERR_ARG, "density must be positive");
+  if (model == EP_LINEAR) {
+    if (n != 2) return fail(c, EP_ERR_ARG, "EP_LINEAR takes {E, nu}");
+    if (!(p[0] > 0.0) || !(p[1] > -1.0 && p[1] < 0.5)) return fail(c, EP_ERR_ARG, "need E > 0 and -1 < nu < 0.5");
+  } else if (model == EP_NH) {
+    if (n != 2) return fail(c, EP_ERR_ARG, "EP_NH takes {mu, lambda}");
+    if (!(p[0] > 0.0) || !(p[1] >= 0.0)) return fail(c, EP_ERR_ARG, "need mu > 0 and lambda >= 0");
+  } else if (model == EP_YEOH) {
+    if (n != 4) return fail(c, EP_ERR_ARG, "EP_YEOH takes {C10, C20, C30, D1}");
+    if (!(p[0] > 0.0) || !(p[3] > 0.0)) return fail(c, EP_ERR_ARG, "need C10 > 0 and D1 > 0");
+  } else {
+    return fail(c, EP_ERR_ARG, "unknown material model");
+  }
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return fail(c, EP_ERR_ARG, "non-finite material parameter");
+  return EP_OK;
+}
+
+static ep_status check_traction(ep_ctx* c, int64_t n_nodes, int64_t n_faces, const int32_t* fn, const double* t0,
+                                int64_t n_knots, const double* kt, const double* ks) {
+  if (n_faces < 0 || n_knots < 0) return fail(c, EP_ERR_ARG, "negative count");
+  if (n_faces > 0 && (!fn || !t0)) return fail(c, EP_ERR_ARG, "null face array or traction");
+  for (int64_t i = 0; i < 4 * n_faces; ++i)
+    if (fn[i] < 0 || fn[i] >= n_nodes) return fail(c, EP_ERR_ARG, "face node out of range");
+  if (n_faces > 0)
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(t0[i])) return fail(c, EP_ERR_ARG, "non-finite traction");
+  if (n_knots > kMaxKnots) return fail(c, EP_ERR_ARG, "too many load knots");
+  if (n_knots > 0 && (!kt || !ks)) return fail(c, EP_ERR_ARG, "null load table");
+  for (int64_t i = 0; i < n_knots; ++i) {
+    if (!std::isfinite(kt[i]) || !std::isfinite(ks[i])) return fail(c, EP_ERR_ARG, "non-finite load table");
+    if (i > 0 && !(kt[i] > kt[i - 1])) return fail(c, EP_ERR_ARG, "load knot times must be ascending");
+  }
+  return EP_OK;
+}
+
+static void fill_mesh(Inst& I, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn) {
+  I.n_nodes = n_nodes;
+  I.n_elems = n_elems;
+  I.xyz.assign(xyz, xyz + 3 * n_nodes);
+  I.conn.assign(conn, conn + 8 * n_elems);
+  I.n3 = (int)(3 * n_nodes);
+  I.L = 2 * I.n3 + 1;
+  I.Lp = (I.L + 63) / 64 * 64;
+}
+
+static void fill_traction(Inst& I, int64_t n_faces, const int32_t* fn, const double* t0, int64_t n_knots,
+                          const double* kt, const double* ks) {
+  I.faces.assign(fn ? fn : (const int32_t*)nullptr, fn ? fn + 4 * n_faces : (const int32_t*)nullptr);
+  for (int i = 0; i < 3; ++i) I.t0[i] = (n_faces > 0 && t0) ? t0[i] : 0.0;
+  I.n_knots = (int)n_knots;
+  I.knots.assign(2 * n_knots, 0.0);
+  for (int64_t i = 0; i < n_knots; ++i) {
+    I.knots[i] = kt[i];
+    I.knots[n_knots + i] = ks[i];
+  }
+}
+
+// ------------------------------------------------------------------------------ layout
+static int pick_G(const ep_ctx* c, const Inst& I, int* chunk) {
+  const int maxG = std::max(1, c->cus);
+  int G = c->G_user > 0 ? c->G_user : (int)std::min<long long>(maxG, std::max<long long>(1, (I.Lp + 4095) / 4096));
+  G = std::max(1, std::min(G, std::min(I.Lp / 64 > 0 ? I.Lp / 64 : 1, 1024)));
+  int C = (I.Lp + G - 1) / G;
+  C = (C + 63) / 64 * 64;
+  *chunk = C;
+  return G;
+}
+
+static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
+  const size_t n3 = I.n3, ne = I.n_elems, nn = I.n_nodes, nf = I.faces.size() / 4;
+  const size_t Lp = I.Lp, mm = c->cfg.m_max;
+  I.o_xyz = L.take(8 * 3 * nn);
+  I.o_conn = L.take(4 * 8 * ne);
+  I.o_incp = L.take(4 * (nn + 1));
+  I.o_inc = L.take(4 * 8 * ne);
+  I.o_geo = L.take(8 * 80 * ne);
+  I.o_geo32 = L.take(4 * 80 * ne);
+  I.o_vdet = L.take(8 * 8 * ne);
+  I.o_mih = L.take(8 * n3);
+  I.o_mh = L.take(8 * n3);
+  I.o_p0 = L.take(8 * n3);
+  I.o_p0bar = L.take(8 * n3);
+  I.o_faces = L.take(4 * 4 * std::max<size_t>(nf, 1));
+  I.o_fincp = L.take(4 * (nn + 1));
+  I.o_finc = L.take(4 * 4 * std::max<size_t>(nf, 1));
+  I.o_ff = L.take(8 * 12 * std::max<size_t>(nf, 1));
+  I.o_knots = L.take(8 * std::max<size_t>(I.knots.size(), 2));
+  I.o_clamp = L.take(n3);
+  I.o_S = L.take(8 * Lp);
+  I.o_X = L.take(8 * Lp);
+  I.o_Wun = L.take(8 * Lp);
+  I.o_V = L.take(8 * Lp * (mm + 1));
+  I.o_F = L.take(8 * 24 * ne);
+  I.o_F32 = L.take(4 * 24 * ne);
+  I.o_hist = L.take(8 * 3 * n3);
+  I.o_stage = L.take(8 * 2 * n3);
+  I.o_slots = L.take(8 * 2 * (size_t)std::max(Gmax, 1));
+  I.o_H = L.take(8 * (mm + 1) * mm);
+  I.o_Escr = L.take(8 * 9 * mm * mm);     // 8 m^2 expm work + m^2 output staging
+  I.o_y = L.take(8 * (mm + 1));
+  I.o_ctrl = L.take(sizeof(Ctrl));
+  I.o_log = L.take(sizeof(StepLog));
+  I.o_pe = L.take(8 * ((ne + 255) / 256 + 1));
+  I.o_pv = L.take(8 * 2 * ((n3 + 255) / 256 + 1));
+  I.o_eout = L.take(8 * 4);
+  I.o_flags = L.take(4 * 4);
+}
+
+static size_t plan_all(ep_ctx* c) {
+  Layout L;
+  const int Gmax = std::max(1, std::max(c->cus, c->G_user));
+  if (!c->batch) {
+    plan_inst(c, c->one, L, Gmax);
+  } else {
+    for (auto& I : c->insts) plan_inst(c, I, L, 1);
+    c->o_batch_tab = L.take(sizeof(ExpvArgs) * std::max<size_t>(c->insts.size(), 1) * 2);
+  }
+  return L.off + kAlign;
+}
+
+// incidence lists (integer bookkeeping)
+static void build_incidence(Inst& I) {
+  const int64_t nn = I.n_nodes, ne = I.n_elems;
+  I.inc_ptr.assign(nn + 1, 0);
+  for (int64_t e = 0; e < ne; ++e)
+    for (int a = 0; a < 8; ++a) I.inc_ptr[I.conn[e * 8 + a] + 1]++;
+  for (int64_t n = 0; n < nn; ++n) I.inc_ptr[n + 1] += I.inc_ptr[n];
+  I.inc.assign(8 * ne, 0);
+  std::vector<int32_t> pos(I.inc_ptr.begin(), I.inc_ptr.end() - 1);
+  for (int a = 0; a < 8; ++a)          // slot-major order: a outer, e inner
+    for (int64_t e = 0; e < ne; ++e) I.inc[pos[I.conn[e * 8 + a]]++] = (int32_t)(a * ne + e);
+  const int64_t nf = I.faces.size() / 4;
+  I.finc_ptr.assign(nn + 1, 0);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int b = 0; b < 4; ++b) I.finc_ptr[I.faces[f * 4 + b] + 1]++;
+  for (int64_t n = 0; n < nn; ++n) I.finc_ptr[n + 1] += I.finc_ptr[n];
+  I.finc.assign(std::max<int64_t>(4 * nf, 1), 0);
+  std::vector<int32_t> fp(I.finc_ptr.begin(), I.finc_ptr.end() - 1);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int b = 0; b < 4; ++b) I.finc[fp[I.faces[f * 4 + b]]++] = (int32_t)(f * 4 + b);
+  I.clamp_mask.assign(I.n3, 0);
+  for (int32_t d : I.clamped) I.clamp_mask[d] = 1;
+}
+
+template <typename P>
+static P* dptr(ep_ctx* c, size_t off) {
+  return reinterpret_cast<P*>(c->ws + off);
+}
+
+static double auto_s0(const ep_ctx* c, const Inst& I) {
+  if (c->s0_user >= 0.0) return c->s0_user;
+  bool load = !I.faces.empty() && (I.t0[0] != 0.0 || I.t0[1] != 0.0 || I.t0[2] != 0.0);
+  bool nonzero_scale = false;
+  for (int i = 0; i < I.n_knots; ++i) nonzero_scale |= I.knots[I.n_knots + i] != 0.0;
+  return (load && nonzero_scale) ? 1.0 : 0.0;
+}
+
+static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk) {
+  hipStream_t st = c->stream;
+  build_incidence(I);
+  const size_t nf = I.faces.size() / 4;
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_xyz), I.xyz.data(), 8 * I.xyz.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_conn), I.conn.data(), 4 * I.conn.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_incp), I.inc_ptr.data(), 4 * I.inc_ptr.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_inc), I.inc.data(), 4 * I.inc.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_fincp), I.finc_ptr.data(), 4 * I.finc_ptr.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_finc), I.finc.data(), 4 * I.finc.size(), hipMemcpyHostToDevice, st));
+  if (nf > 0)
+    EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_faces), I.faces.data(), 4 * I.faces.size(), hipMemcpyHostToDevice, st));
+  if (!I.knots.empty())
+    EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_knots), I.knots.data(), 8 * I.knots.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_clamp), I.clamp_mask.data(), I.clamp_mask.size(), hipMemcpyHostToDevice, st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_flags), 0, 16, st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_S), 0, 8 * (size_t)I.Lp, st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_X), 0, 8 * (size_t)I.Lp, st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_Wun), 0, 8 * (size_t)I.Lp, st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_hist), 0, 8 * 3 * (size_t)I.n3, st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_log), 0, sizeof(StepLog), st));
+  EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_H), 0, 8 * (size_t)(c->cfg.m_max + 1) * c->cfg.m_max, st));
+  int* flags = dptr<int>(c, I.o_flags);
+  launch_geometry(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_conn), (int)I.n_elems, dptr<double>(c, I.o_geo),
+                  dptr<float>(c, I.o_geo32), dptr<double>(c, I.o_vdet), flags + 0, st);
+  launch_congruence(dptr<double>(c, I.o_geo), (int)I.n_elems, flags + 1, st);
+  EP_HIP(c, hipGetLastError());
+  launch_mass((int)I.n_nodes, (int)I.n_elems, dptr<int>(c, I.o_incp), dptr<int>(c, I.o_inc),
+              dptr<double>(c, I.o_vdet), I.rho, dptr<unsigned char>(c, I.o_clamp), dptr<double>(c, I.o_mih),
+              dptr<double>(c, I.o_mh), st);
+  launch_faces(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_faces), (int)nf, I.t0, dptr<double>(c, I.o_ff),
+               (int)I.n_nodes, dptr<int>(c, I.o_fincp), dptr<int>(c, I.o_finc), dptr<double>(c, I.o_mih),
+               dptr<double>(c, I.o_p0), dptr<double>(c, I.o_p0bar), st);
+  EP_HIP(c, hipGetLastError());
+  int hflags[2] = {0, 0};
+  EP_HIP(c, hipMemcpyAsync(hflags, flags, 8, hipMemcpyDeviceToHost, st));
+  EP_HIP(c, hipStreamSynchronize(st));
+  if (hflags[0]) return fail(c, EP_ERR_INVERTED, "inverted or degenerate reference element (det J <= 0)");
+  Mesh& M = I.M;
+  M.n_nodes = (int)I.n_nodes;
+  M.n_elems = (int)I.n_elems;
+  M.n3 = I.n3;
+  M.L = I.L;
+  M.Lp = I.Lp;
+  M.conn = dptr<int>(c, I.o_conn);
+  M.inc_ptr = dptr<int>(c, I.o_incp);
+  M.inc = dptr<int>(c, I.o_inc);
+  M.geo = dptr<double>(c, I.o_geo);
+  M.geo32 = dptr<float>(c, I.o_geo32);
+  M.congruent = hflags[1] ? 0 : 1;
+  M.mih = dptr<double>(c, I.o_mih);
+  M.mh = dptr<double>(c, I.o_mh);
+  M.p0bar = dptr<double>(c, I.o_p0bar);
+  M.p0 = dptr<double>(c, I.o_p0);
+  M.knots = dptr<double>(c, I.o_knots);
+  M.n_knots = I.n_knots;
+  M.model = I.model;
+  for (int i = 0; i < 4; ++i) M.mp[i] = I.mp[i];
+  M.s0 = auto_s0(c, I);
+  M.s_inv = M.s0 != 0.0 ? 1.0 / M.s0 : 0.0;
+  KWork& W = I.W;
+  W.V = dptr<double>(c, I.o_V);
+  W.Wun = dptr<double>(c, I.o_Wun);
+  W.X = dptr<double>(c, I.o_X);
+  W.F = dptr<double>(c, I.o_F);
+  W.F32 = dptr<float>(c, I.o_F32);
+  W.slots = dptr<double>(c, I.o_slots);
+  W.H = dptr<double>(c, I.o_H);
+  W.Escr = dptr<double>(c, I.o_Escr);
+  W.y = dptr<double>(c, I.o_y);
+  W.ctrl = dptr<Ctrl>(c, I.o_ctrl);
+  W.log = dptr<StepLog>(c, I.o_log);
+  W.G = G;
+  W.chunk = chunk;
+  launch_reset_ctrl(W.ctrl, st);
+  EP_HIP(c, hipGetLastError());
+  EP_HIP(c, hipStreamSynchronize(st));
+  return EP_OK;
+}
+
+static ep_status read_err(ep_ctx* c, Inst& I) {
+  int e = 0;
+  EP_HIP(c, hipMemcpyAsync(&e, &I.W.ctrl->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  if (e == 0) return EP_OK;
+  const char* what = e == kErrKrylov ? "Krylov error estimate above tol at m_max after the allowed substeps"
+                     : e == kErrInverted ? "det F <= 0 at a Gauss point (inverted deformation)"
+                     : e == kErrNonfinite ? "non-finite value in the Krylov recurrence"
+                     : e == kErrDevice ? "device synchronisation timed out"
+                                       : "device error";
+  return fail(c, (ep_status)e, what);
+}
+
+// ------------------------------------------------------------------------------ stepping
+static OpArgs op_linear(double tau, double t_eval) {
+  OpArgs op{};
+  op.tau = tau;
+  op.t_eval = t_eval;
+  op.nsets = 0;
+  return op;
+}
+
+static ep_status run_expv(ep_ctx* c, Inst& I, const OpArgs& op, int kind, const double* xin, double* xout, int mode,
+                          int log_idx) {
+  ExpvArgs a{};
+  a.M = I.M;
+  a.W = I.W;
+  a.cfg = c->cfg;
+  a.op = op;
+  a.kind = kind;
+  a.x_in = xin;
+  a.x_out = xout;
+  a.out_mode = mode;
+  a.log_idx = log_idx;
+  EP_HIP(c, launch_expv(a, c->cfg.prec, c->stream));
+  return EP_OK;
+}
+
+static double* hist_slot(ep_ctx* c, Inst& I, int s) { return dptr<double>(c, I.o_hist) + (size_t)s * I.n3; }
+
+static int free_slot(const Inst& I) {
+  for (int s = 0; s < 3; ++s)
+    if (s != I.hist_new && s != I.hist_old) return s;
+  return 0;
+}
+
+static ep_status step_one(ep_ctx* c, Inst& I, double dt) {
+  double* S = dptr<double>(c, I.o_S);
+  const double t = I.t;
+  const int log_idx = (int)(I.step_idx % kLogSteps);
+  if (I.model == EP_LINEAR) {
+    ep_status s = run_expv(c, I, op_linear(dt, t + 0.5 * dt), 0, S, S, 0, log_idx);
+    if (s != EP_OK) return s;
+  } else {
+    OpArgs pred{};
+    pred.tau = 0.5 * dt;
+    pred.t_eval = t + 0.25 * dt;
+    if (I.nhist == 0) {
+      // first step: H(u_0) at the current displacement
+      const int s0 = free_slot(I);
+      launch_get_state(I.n3, I.M.mih, S, hist_slot(c, I, s0), nullptr, c->stream);
+      EP_HIP(c, hipGetLastError());
+      pred.nsets = 1;
+      pred.ulin[0] = hist_slot(c, I, s0);
+      pred.wts[0] = 1.0;
+      I.hist_old = s0;   // reserve while the predictor reads it
+    } else if (I.nhist == 1) {
+      pred.nsets = 1;
+      pred.ulin[0] = hist_slot(c, I, I.hist_new);
+      pred.wts[0] = 1.0;
+    } else {
+      pred.nsets = 2;
+      pred.ulin[0] = hist_slot(c, I, I.hist_new);
+      pred.wts[0] = 1.75;
+      pred.ulin[1] = hist_slot(c, I, I.hist_old);
+      pred.wts[1] = -0.75;
+    }
+    const int snew = free_slot(I);
+    ep_status s = run_expv(c, I, pred, 1, S, hist_slot(c, I, snew), 1, log_idx);
+    if (s != EP_OK) return s;
+    OpArgs corr{};
+    corr.tau = dt;
+    corr.t_eval = t + 0.5 * dt;
+    corr.nsets = 1;
+    corr.ulin[0] = hist_slot(c, I, snew);
+    corr.wts[0] = 1.0;
+    s = run_expv(c, I, corr, 0, S, S, 0, log_idx);
+    if (s != EP_OK) return s;
+    if (I.nhist == 0) {
+      I.hist_old = -1;
+      I.hist_new = snew;
+      I.nhist = 1;
+    } else {
+      I.hist_old = I.hist_new;
+      I.hist_new = snew;
+      I.nhist = 2;
+    }
+  }
+  I.t = t + dt;
+  I.step_idx += 1;
+  return EP_OK;
+}
+
+// ============================================================================== C ABI
+extern "C" {
+
+const char* ep_version(void) { return "ep-mi355x 0.1 (gfx950)"; }
+
+ep_status ep_create(ep_ctx** out, int hip_device) {
+  if (!out) return EP_ERR_ARG;
+  *out = nullptr;
+  if (hip_device < -1) return EP_ERR_ARG;
+  ep_ctx* c = new (std::nothrow) ep_ctx();
+  if (!c) return EP_ERR_ARG;
+  c->device = hip_device;
+  if (hip_device >= 0) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device >= n) {
+      delete c;
+      return EP_ERR_HIP;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) {
+      delete c;
+      return EP_ERR_HIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+      delete c;
+      return EP_ERR_HIP;
+    }
+    c->cus = prop.multiProcessorCount;
+  } else {
+    c->cus = 256;
+  }
+  *out = c;
+  return EP_OK;
+}
+
+ep_status ep_destroy(ep_ctx* c) {
+  if (!c) return EP_ERR_ARG;
+  delete c;
+  return EP_OK;
+}
+
+const char* ep_last_error(const ep_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+ep_status ep_set_stream(ep_ctx* c, void* s) {
+  if (!c) return EP_ERR_ARG;
+  c->stream = reinterpret_cast<hipStream_t>(s);
+  return EP_OK;
+}
+
+ep_status ep_set_mesh_hex8(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
+  if (c->batch) return fail(c, EP_ERR_ORDER, "batch context: use ep_batch_add_instance");
+  ep_status s = check_mesh(c, n_nodes, xyz, n_elems, conn);
+  if (s != EP_OK) return s;
+  fill_mesh(c->one, n_nodes, xyz, n_elems, conn);
+  c->one.clamped.clear();
+  c->one.faces.clear();
+  c->one.n_knots = 0;
+  c->one.knots.clear();
+  c->mesh_set = true;
+  return EP_OK;
+}
+
+ep_status ep_set_material(ep_ctx* c, ep_model model, const double* p, int n, double rho) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
+  ep_status s = check_material(c, (int)model, p, n, rho);
+  if (s != EP_OK) return s;
+  c->one.model = (int)model;
+  for (int i = 0; i < 4; ++i) c->one.mp[i] = i < n ? p[i] : 0.0;
+  c->one.rho = rho;
+  c->material_set = true;
+  return EP_OK;
+}
+
+ep_status ep_set_dirichlet(ep_ctx* c, int64_t n, const int32_t* ids) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
+  if (!c->mesh_set) return fail(c, EP_ERR_ORDER, "ep_set_dirichlet before ep_set_mesh_hex8");
+  if (n < 0 || (n > 0 && !ids)) return fail(c, EP_ERR_ARG, "bad Dirichlet list");
+  for (int64_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= c->one.n3) return fail(c, EP_ERR_ARG, "Dirichlet DOF out of range");
+  c->one.clamped.assign(ids, ids + n);
+  return EP_OK;
+}
+
+ep_status ep_set_traction(ep_ctx* c, int64_t n_faces, const int32_t* fn, const double t0[3], int64_t n_knots,
+                          const double* kt, const double* ks) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
+  if (!c->mesh_set) return fail(c, EP_ERR_ORDER, "ep_set_traction before ep_set_mesh_hex8");
+  ep_status s = check_traction(c, c->one.n_nodes, n_faces, fn, t0, n_knots, kt, ks);
+  if (s != EP_OK) return s;
+  fill_traction(c->one, n_faces, fn, t0, n_knots, kt, ks);
+  return EP_OK;
+}
+
+ep_status ep_set_krylov(ep_ctx* c, double tol, int m_max, int check_every, int m_fixed, int k_fixed,
+                        int max_substeps, double s0) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "ep_set_krylov after ep_bind_workspace");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(c, EP_ERR_ARG, "tol must be positive");
+  if (m_max < 1 || m_max > kMaxM) return fail(c, EP_ERR_ARG, "m_max must be in [1, 256]");
+  if (check_every < 1) return fail(c, EP_ERR_ARG, "check_every must be >= 1");
+  if (m_fixed < 0 || m_fixed > m_max) return fail(c, EP_ERR_ARG, "m_fixed must be in [0, m_max]");
+  if (k_fixed < 0 || max_substeps < 1 || k_fixed > (1 << 20)) return fail(c, EP_ERR_ARG, "bad substep settings");
+  if (!std::isfinite(s0)) return fail(c, EP_ERR_ARG, "s0 must be finite");
+  c->cfg.tol = tol;
+  c->cfg.m_max = m_max;
+  c->cfg.check_every = check_every;
+  c->cfg.m_fixed = m_fixed;
+  c->cfg.k_fixed = k_fixed;
+  c->cfg.max_substeps = max_substeps;
+  c->s0_user = s0;
+  return EP_OK;
+}
+
+ep_status ep_set_precision(ep_ctx* c, ep_precision p) {
+  if (!c) return EP_ERR_ARG;
+  if (p != EP_PREC_F64 && p != EP_PREC_MIXED_F32) return fail(c, EP_ERR_ARG, "unknown precision");
+  c->cfg.prec = (int)p;
+  return EP_OK;
+}
+
+ep_status ep_set_launch(ep_ctx* c, int G) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "ep_set_launch after ep_bind_workspace");
+  if (G < 0 || G > 1024) return fail(c, EP_ERR_ARG, "workgroups must be in [0, 1024]");
+  c->G_user = G;
+  return EP_OK;
+}
+
+ep_status ep_workspace_size(ep_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return EP_ERR_ARG;
+  if (!c->batch && (!c->mesh_set || !c->material_set))
+    return fail(c, EP_ERR_ORDER, "workspace size needs the mesh and the material");
+  if (c->batch && c->insts.empty()) return fail(c, EP_ERR_ORDER, "batch has no instances");
+  *bytes = plan_all(c);
+  return EP_OK;
+}
+
+ep_status ep_batch_bind(ep_ctx* c);   // ep_batch.cpp
+
+ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "workspace already bound");
+  size_t need = 0;
+  ep_status s = ep_workspace_size(c, &need);
+  if (s != EP_OK) return s;
+  if (!p) return fail(c, EP_ERR_ARG, "null workspace");
+  if (reinterpret_cast<uintptr_t>(p) % kAlign != 0) return fail(c, EP_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (bytes < need) return fail(c, EP_ERR_WORKSPACE, "workspace too small");
+  if (!is_gpu(c)) return fail(c, EP_ERR_HIP, "host-only context cannot bind device memory");
+  EP_HIP(c, hipSetDevice(c->device));
+  c->ws = reinterpret_cast<char*>(p);
+  c->ws_bytes = bytes;
+  if (c->batch) {
+    s = ep_batch_bind(c);
+    if (s != EP_OK) return s;
+  } else {
+    int chunk = 0;
+    int G = pick_G(c, c->one, &chunk);
+    // cooperative residency: shrink G until it fits
+    int bpc = 0;
+    for (;;) {
+      EP_HIP(c, expv_max_blocks(c->cfg.prec, c->one.model, chunk, &bpc));
+      if ((long long)bpc * c->cus >= G || G == 1) break;
+      G = std::max(1, (int)((long long)bpc * c->cus));
+      chunk = ((c->one.Lp + G - 1) / G + 63) / 64 * 64;
+    }
+    if (bpc < 1) return fail(c, EP_ERR_WORKSPACE, "Krylov vector slice does not fit in LDS");
+    s = setup_inst(c, c->one, G, chunk);
+    if (s != EP_OK) return s;
+  }
+  c->bound = true;
+  return EP_OK;
+}
+
+static ep_status need_bound(ep_ctx* c) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound) return fail(c, EP_ERR_ORDER, "call ep_bind_workspace first");
+  if (c->batch) return fail(c, EP_ERR_ORDER, "batch context: use the ep_batch_* calls");
+  return EP_OK;
+}
+
+ep_status ep_set_state(ep_ctx* c, double t, const double* u, const double* v) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!u || !v || !std::isfinite(t)) return fail(c, EP_ERR_ARG, "bad state arguments");
+  Inst& I = c->one;
+  for (int i = 0; i < I.n3; ++i)
+    if (!std::isfinite(u[i]) || !std::isfinite(v[i])) return fail(c, EP_ERR_ARG, "non-finite state");
+  double* st = dptr<double>(c, I.o_stage);
+  EP_HIP(c, hipMemcpyAsync(st, u, 8 * (size_t)I.n3, hipMemcpyHostToDevice, c->stream));
+  EP_HIP(c, hipMemcpyAsync(st + I.n3, v, 8 * (size_t)I.n3, hipMemcpyHostToDevice, c->stream));
+  launch_set_state(I.n3, I.Lp, I.M.mh, st, st + I.n3, I.M.s0, dptr<double>(c, I.o_S), c->stream);
+  launch_reset_ctrl(I.W.ctrl, c->stream);
+  EP_HIP(c, hipGetLastError());
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  I.t = t;
+  I.step_idx = 0;
+  I.nhist = 0;
+  I.hist_new = I.hist_old = -1;
+  I.state_set = true;
+  return EP_OK;
+}
+
+ep_status ep_step(ep_ctx* c, double dt, int64_t n) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!c->one.state_set) return fail(c, EP_ERR_ORDER, "call ep_set_state first");
+  if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return fail(c, EP_ERR_ARG, "need dt > 0 and n_steps >= 0");
+  for (int64_t i = 0; i < n; ++i) {
+    s = step_one(c, c->one, dt);
+    if (s != EP_OK) return s;
+  }
+  return EP_OK;
+}
+
+ep_status ep_sync(ep_ctx* c) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound) return fail(c, EP_ERR_ORDER, "call ep_bind_workspace first");
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  if (c->batch) {
+    for (auto& I : c->insts) {
+      ep_status s = read_err(c, I);
+      if (s != EP_OK) return s;
+    }
+    return EP_OK;
+  }
+  return read_err(c, c->one);
+}
+
+ep_status ep_get_state(ep_ctx* c, double* t, double* u, double* v) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!t || !u || !v) return fail(c, EP_ERR_ARG, "null output");
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  double* st = dptr<double>(c, I.o_stage);
+  launch_get_state(I.n3, I.M.mih, dptr<double>(c, I.o_S), st, st + I.n3, c->stream);
+  EP_HIP(c, hipGetLastError());
+  EP_HIP(c, hipMemcpyAsync(u, st, 8 * (size_t)I.n3, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipMemcpyAsync(v, st + I.n3, 8 * (size_t)I.n3, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  *t = I.t;
+  return EP_OK;
+}
+
+ep_status ep_get_energy(ep_ctx* c, double* ke, double* se, double* we) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!ke || !se || !we) return fail(c, EP_ERR_ARG, "null output");
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  double* out = dptr<double>(c, I.o_eout);
+  launch_energy(I.M, dptr<double>(c, I.o_S), I.t, dptr<double>(c, I.o_pe), dptr<double>(c, I.o_pv), out, c->stream);
+  EP_HIP(c, hipGetLastError());
+  double h[3];
+  EP_HIP(c, hipMemcpyAsync(h, out, 24, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  *ke = h[0];
+  *se = h[1];
+  *we = h[2];
+  return EP_OK;
+}
+
+ep_status ep_get_stats(ep_ctx* c, int64_t* matvecs, int* last_m, double* last_eps, int* last_k, double* drift) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  Ctrl h;
+  EP_HIP(c, hipMemcpy(&h, c->one.W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  if (matvecs) *matvecs = h.ks[0].matvecs + h.ks[1].matvecs;
+  if (last_m) *last_m = h.ks[0].last_m;
+  if (last_eps) *last_eps = h.ks[0].last_eps;
+  if (last_k) *last_k = h.ks[0].last_k;
+  if (drift) *drift = h.drift;
+  return EP_OK;
+}
+
+ep_status ep_get_step_log(ep_ctx* c, int n, int32_t* m_corr, int32_t* m_pred, int32_t* k_corr, double* eps_corr) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (n < 0 || n > kLogSteps) return fail(c, EP_ERR_ARG, "n must be in [0, 4096]");
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  std::vector<StepLog> h(1);
+  EP_HIP(c, hipMemcpy(h.data(), c->one.W.log, sizeof(StepLog), hipMemcpyDeviceToHost));
+  const int64_t end = c->one.step_idx;
+  for (int i = 0; i < n; ++i) {
+    const int64_t idx = end - n + i;
+    const int sl = (int)(((idx % kLogSteps) + kLogSteps) % kLogSteps);
+    const bool ok = idx >= 0;
+    if (m_corr) m_corr[i] = ok ? h[0].m_corr[sl] : 0;
+    if (m_pred) m_pred[i] = ok ? h[0].m_pred[sl] : 0;
+    if (k_corr) k_corr[i] = ok ? h[0].k_corr[sl] : 0;
+    if (eps_corr) eps_corr[i] = ok ? h[0].eps_corr[sl] : 0.0;
+  }
+  return EP_OK;
+}
+
+// --------------------------------------------------------------------------- stage calls
+static OpArgs op_from(const double* ulin, double tau, double t_eval) {
+  OpArgs op{};
+  op.tau = tau;
+  op.t_eval = t_eval;
+  op.nsets = ulin ? 1 : 0;
+  op.ulin[0] = ulin;
+  op.wts[0] = 1.0;
+  return op;
+}
+
+ep_status ep_apply_H(ep_ctx* c, const double* u_lin, const double* x, double* y) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!x || !y) return fail(c, EP_ERR_ARG, "null vector");
+  Inst& I = c->one;
+  launch_apply_H(I.M, op_from(u_lin, 1.0, 0.0), c->cfg.prec, x, y, I.W.F, I.W.F32, &I.W.ctrl->err, c->stream);
+  EP_HIP(c, hipGetLastError());
+  return ep_sync(c);
+}
+
+ep_status ep_vector_length(ep_ctx* c, int64_t* len, int64_t* padded) {
+  if (!c || !len || !padded) return EP_ERR_ARG;
+  if (c->batch || !c->mesh_set) return fail(c, EP_ERR_ORDER, "needs a single-instance mesh");
+  *len = c->one.L;
+  *padded = c->one.Lp;
+  return EP_OK;
+}
+
+ep_status ep_apply_A(ep_ctx* c, const double* u_lin, double tau, double pscale, const double* x, double* y) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!x || !y || !std::isfinite(tau) || !std::isfinite(pscale)) return fail(c, EP_ERR_ARG, "bad arguments");
+  Inst& I = c->one;
+  // the load scale is passed through a one-knot table evaluated at t = 0
+  Mesh M = I.M;
+  double* kn = dptr<double>(c, I.o_stage);
+  double h2[2] = {0.0, pscale};
+  EP_HIP(c, hipMemcpyAsync(kn, h2, 16, hipMemcpyHostToDevice, c->stream));
+  M.knots = kn;
+  M.n_knots = 1;
+  launch_apply_A(M, op_from(u_lin, tau, 0.0), c->cfg.prec, x, y, I.W.F, I.W.F32, &I.W.ctrl->err, c->stream);
+  EP_HIP(c, hipGetLastError());
+  return ep_sync(c);
+}
+
+ep_status ep_expm(ep_ctx* c, int m, const double* H, double* E) {
+  if (!c) return EP_ERR_ARG;
+  if (m < 1 || m > kMaxM || !H || !E) return fail(c, EP_ERR_ARG, "need 1 <= m <= 256 and host arrays");
+  for (int i = 0; i < m * m; ++i)
+    if (!std::isfinite(H[i])) return fail(c, EP_ERR_ARG, "non-finite matrix entry");
+  if (!c->bound || c->batch) return fail(c, EP_ERR_ORDER, "call ep_bind_workspace first");
+  Inst& I = c->one;
+  if (m > c->cfg.m_max) return fail(c, EP_ERR_ARG, "m exceeds the m_max the workspace was sized for");
+  double* dH = I.W.H;
+  double* dE = I.W.Escr + (size_t)8 * c->cfg.m_max * c->cfg.m_max;
+  EP_HIP(c, hipMemcpyAsync(dH, H, 8 * (size_t)m * m, hipMemcpyHostToDevice, c->stream));
+  launch_expm(m, dH, dE, I.W.Escr, c->stream);
+  EP_HIP(c, hipGetLastError());
+  EP_HIP(c, hipMemcpyAsync(E, dE, 8 * (size_t)m * m, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  return EP_OK;
+}
+
+ep_status ep_arnoldi(ep_ctx* c, const double* u_lin, double tau, double pscale, const double* w, int m, double* V,
+                     double* H, int* steps) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  if (!w || !H || !steps || m < 1 || m > c->cfg.m_max) return fail(c, EP_ERR_ARG, "bad arguments");
+  double* kn = dptr<double>(c, I.o_stage);
+  double h2[2] = {0.0, pscale};
+  EP_HIP(c, hipMemcpyAsync(kn, h2, 16, hipMemcpyHostToDevice, c->stream));
+  ExpvArgs a{};
+  a.M = I.M;
+  a.M.knots = kn;
+  a.M.n_knots = 1;
+  a.W = I.W;
+  a.cfg = c->cfg;
+  a.cfg.m_fixed = m;
+  a.cfg.k_fixed = 1;
+  a.op = op_from(u_lin, tau, 0.0);
+  a.kind = 2;
+  a.x_in = w;
+  a.x_out = I.W.X;   // result discarded
+  a.out_mode = 2;
+  a.log_idx = -1;
+  EP_HIP(c, hipMemsetAsync(I.W.H, 0, 8 * (size_t)(c->cfg.m_max + 1) * c->cfg.m_max, c->stream));
+  EP_HIP(c, launch_expv(a, c->cfg.prec, c->stream));
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  Ctrl h;
+  EP_HIP(c, hipMemcpy(&h, I.W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  *steps = h.ks[2].last_m;
+  const int ld = c->cfg.m_max;
+  std::vector<double> Hs((size_t)(ld + 1) * ld);
+  EP_HIP(c, hipMemcpy(Hs.data(), I.W.H, 8 * Hs.size(), hipMemcpyDeviceToHost));
+  for (int i = 0; i <= m; ++i)
+    for (int j = 0; j < m; ++j) H[(size_t)i * m + j] = Hs[(size_t)i * ld + j];
+  if (V) EP_HIP(c, hipMemcpy(V, I.W.V, 8 * (size_t)I.Lp * (m + 1), hipMemcpyDeviceToDevice));
+  return EP_OK;
+}
+
+ep_status ep_expv(ep_ctx* c, const double* u_lin, double tau, double pscale, const double* w, double* y, int* m_used,
+                  int* k_used, double* eps) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  if (!w || !y || !std::isfinite(tau)) return fail(c, EP_ERR_ARG, "bad arguments");
+  double* kn = dptr<double>(c, I.o_stage);
+  double h2[2] = {0.0, pscale};
+  EP_HIP(c, hipMemcpyAsync(kn, h2, 16, hipMemcpyHostToDevice, c->stream));
+  ExpvArgs a{};
+  a.M = I.M;
+  a.M.knots = kn;
+  a.M.n_knots = 1;
+  a.W = I.W;
+  a.cfg = c->cfg;
+  a.op = op_from(u_lin, tau, 0.0);
+  a.kind = 2;
+  a.x_in = w;
+  a.x_out = y;
+  a.out_mode = 2;
+  a.log_idx = -1;
+  EP_HIP(c, launch_expv(a, c->cfg.prec, c->stream));
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  Ctrl h;
+  EP_HIP(c, hipMemcpy(&h, I.W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  if (m_used) *m_used = h.ks[2].last_m;
+  if (k_used) *k_used = h.ks[2].last_k;
+  if (eps) *eps = h.ks[2].last_eps;
+  return EP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,118 @@
+// Shared host/device definitions of the MI355X exponential-propagator library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ep {
+
+constexpr int kThreads = 512;        // workgroup size of every persistent / element kernel
+constexpr int kMaxM = 256;           // largest Krylov subspace
+constexpr int kLogSteps = 4096;      // per-step statistics ring
+constexpr int kMaxKnots = 4096;
+
+// material ids (ep_model)
+constexpr int kLinear = 0, kNH = 1, kYeoh = 2;
+
+// sticky device error codes (match ep_status)
+constexpr int kErrKrylov = -4, kErrInverted = -5, kErrNonfinite = -6, kErrDevice = -8;
+
+// Device view of one mesh instance.  All vectors are node-major doubles; the Krylov
+// vector layout is [ubar (n3) | vbar (n3) | s | zero padding up to Lp].
+struct Mesh {
+  int n_nodes, n_elems, n3;
+  int L, Lp;                  // L = 2*n3 + 1, Lp = padded row stride of V
+  const int* conn;            // [n_elems*8]
+  const int* inc_ptr;         // [n_nodes+1] node -> element-slot CSR
+  const int* inc;             // slot ids a*n_elems + e
+  const double* geo;          // per quadrature point: Jinv (3x3 row major) + w*detJ
+  const float* geo32;
+  int congruent;              // 1: one geometry set shared by all elements
+  const double* mih;          // M^{-1/2} per DOF (0 on clamped DOFs)
+  const double* mh;           // M^{1/2}  per DOF (0 on clamped DOFs)
+  const double* p0bar;        // M^{-1/2} P0 per DOF (0 on clamped DOFs)
+  const double* p0;           // P0 per DOF
+  const double* knots;        // [2*n_knots]: times then scales
+  int n_knots;
+  int model;
+  double mp[4];               // linear (E, nu) | nh (mu, lambda) | yeoh (C10, C20, C30, D1)
+  double s0, s_inv;           // augmented entry value and 1/s0 (0 when s0 == 0)
+};
+
+// Operator tau * A[H(u_lin), pbar(t)] of the augmented first-order system.
+struct OpArgs {
+  double tau;                 // time-step factor (dt / substeps)
+  double t_eval;              // time at which the load scale is evaluated
+  int nsets;                  // 0: H(0) (linear-elastic or rest state); 1 or 2 secant sets
+  const double* ulin[2];      // physical nodal displacements of the secant sets
+  double wts[2];              // weights of the sets (predictor: 1.75, -0.75)
+};
+
+struct KrylovCfg {
+  double tol;
+  int m_max, check_every, m_fixed, k_fixed, max_substeps;
+  int prec;                   // 0 FP64, 1 FP32 element kernels
+};
+
+// Per-projection-kind adaptive state (kept on device between launches).
+struct KState {
+  int k;                      // sticky substep count
+  int m_hint;                 // last converged subspace size
+  int last_m, last_k;
+  double last_eps;
+  long long matvecs;
+};
+
+// Device control block of one instance.
+struct Ctrl {
+  unsigned long long bar;     // grid barrier arrivals (zeroed before every launch)
+  int err;                    // sticky error
+  int pad0;
+  int decision;               // broadcast from workgroup 0
+  int pad1;
+  double bcast[4];
+  KState ks[3];               // 0 = corrector / linear, 1 = predictor, 2 = stage calls
+  int log_pos;
+  int pad2;
+  double drift;
+};
+
+struct StepLog {
+  int m_corr[kLogSteps];
+  int m_pred[kLogSteps];
+  int k_corr[kLogSteps];
+  double eps_corr[kLogSteps];
+};
+
+// Scratch of the persistent Krylov kernel for one instance.
+struct KWork {
+  double* V;                  // (m_max+1) x Lp
+  double* Wun;                // Lp: unnormalised Arnoldi vector
+  double* X;                  // Lp: propagated vector
+  double* F;                  // 24*n_elems element forces (slot-major)
+  float* F32;
+  double* slots;              // 2 * G partial sums
+  double* H;                  // (m_max+1) x m_max Hessenberg (row major, stride m_max)
+  double* Escr;               // expm scratch 8 * m_max^2 (+ m_max^2 output staging)
+  double* y;                  // m_max coefficients
+  Ctrl* ctrl;
+  StepLog* log;
+  int G;                      // workgroups of the team
+  int chunk;                  // Krylov-vector entries owned by each workgroup
+};
+
+// One launch of the persistent projection kernel: wbar_out = exp(tau A) wbar_in.
+struct ExpvArgs {
+  Mesh M;
+  KWork W;
+  KrylovCfg cfg;
+  OpArgs op;
+  int kind;                   // 0: corrector (or linear step), 1: predictor, 2: stage call
+  const double* x_in;         // Lp doubles
+  double* x_out;              // out_mode 0: Lp doubles, augmented entry reset to s0 (drift
+                              // recorded); 1: n3 doubles of M^{-1/2} ubar; 2: Lp doubles as is
+  int out_mode;
+  int log_idx;                // step-log slot (-1: none)
+};
+
+}  // namespace ep

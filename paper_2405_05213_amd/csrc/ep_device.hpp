@@ -1,0 +1,406 @@
+// Device building blocks: hex8 element kernels, constitutive coefficients, reductions and
+// the workgroup-team synchronisation used by the persistent Krylov kernels.
+#pragma once
+
+#include "ep_common.hpp"
+
+namespace ep {
+
+// ---------------------------------------------------------------------------------------
+// hex8 reference element (VTK order) and the 2x2x2 Gauss rule (Sec. 2.2).
+// Node a sits at (sx, sy, sz) in {-1,1}^3; Gauss point q at g * (signs of node q).
+// ---------------------------------------------------------------------------------------
+__host__ __device__ constexpr int node_sx(int a) { return (a == 1 || a == 2 || a == 5 || a == 6) ? 1 : -1; }
+__host__ __device__ constexpr int node_sy(int a) { return (a == 2 || a == 3 || a == 6 || a == 7) ? 1 : -1; }
+__host__ __device__ constexpr int node_sz(int a) { return a >= 4 ? 1 : -1; }
+constexpr double kGauss = 0.57735026918962576451;   // 1/sqrt(3)
+
+// Factors (1 + s g_d) of the Gauss point q for node signs s = +1 (p) and -1 (m).
+template <typename T>
+struct QFactors {
+  T p[3], m[3];
+  __device__ __forceinline__ explicit QFactors(int q) {
+    const int s[3] = {node_sx(q), node_sy(q), node_sz(q)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      p[d] = T(1) + T(kGauss) * T(s[d]);
+      m[d] = T(1) - T(kGauss) * T(s[d]);
+    }
+  }
+  // dN_a / dxi_j at this point (a compile-time after unrolling)
+  __device__ __forceinline__ T dN(int a, int j) const {
+    const int s[3] = {node_sx(a), node_sy(a), node_sz(a)};
+    T f[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) f[d] = s[d] > 0 ? p[d] : m[d];
+    const T eighth = T(0.125);
+    if (j == 0) return eighth * T(s[0]) * f[1] * f[2];
+    if (j == 1) return eighth * T(s[1]) * f[0] * f[2];
+    return eighth * T(s[2]) * f[0] * f[1];
+  }
+};
+
+// Gradient at a Gauss point: G[i][k] = sum_a x[a][i] dN_a/dX_k with dN/dX = dN/dxi Jinv.
+template <typename T>
+__device__ __forceinline__ void grad_at(const QFactors<T>& Q, const T (&x)[8][3], const T* Jinv, T (&G)[3][3]) {
+  T Dxi[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Dxi[i][j] = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T d0 = Q.dN(a, 0), d1 = Q.dN(a, 1), d2 = Q.dN(a, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Dxi[i][0] += x[a][i] * d0;
+      Dxi[i][1] += x[a][i] * d1;
+      Dxi[i][2] += x[a][i] * d2;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      G[i][k] = Dxi[i][0] * Jinv[0 * 3 + k] + Dxi[i][1] * Jinv[1 * 3 + k] + Dxi[i][2] * Jinv[2 * 3 + k];
+}
+
+// f[a][i] += wdet * sum_k S[i][k] dN_a/dX_k
+template <typename T>
+__device__ __forceinline__ void scatter_at(const QFactors<T>& Q, const T (&S)[3][3], const T* Jinv, T wdet,
+                                           T (&f)[8][3]) {
+  T St[3][3];   // wdet * S Jinv^T
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      St[i][j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T d0 = Q.dN(a, 0), d1 = Q.dN(a, 1), d2 = Q.dN(a, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[a][i] += St[i][0] * d0 + St[i][1] * d1 + St[i][2] * d2;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Constitutive coefficients of the secant split R(u) = H(u) u (App. A pattern):
+//   secant(D, X) = a (X + G X^T) + (W : X) G,   G = F^{-T}, F = I + D.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct Secant {
+  T a;
+  T G[3][3];
+  T W[3][3];
+};
+
+__device__ __forceinline__ double ep_log1p(double x) { return log1p(x); }
+__device__ __forceinline__ float ep_log1p(float x) { return log1pf(x); }
+__device__ __forceinline__ double ep_exp(double x) { return exp(x); }
+__device__ __forceinline__ float ep_exp(float x) { return expf(x); }
+
+// ln(1+x)/x, continuous through x = 0
+template <typename T>
+__device__ __forceinline__ T log_ratio(T x) {
+  const T ax = x < T(0) ? -x : x;
+  if (ax < T(sizeof(T) == 8 ? 1e-8 : 1e-4)) return T(1) - T(0.5) * x + x * x / T(3);
+  return ep_log1p(x) / x;
+}
+
+// Returns false if J <= 0 (or not finite).
+template <typename T, int MODEL>
+__device__ __forceinline__ bool secant_coeffs(const T (&D)[3][3], const double* mp, Secant<T>& s) {
+  // polynomial cofactor of D
+  T c[3][3];
+  c[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+  c[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+  c[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+  c[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+  c[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+  c[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+  c[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+  c[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+  c[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+  const T trD = D[0][0] + D[1][1] + D[2][2];
+  // Q = I + (trD I - D^T)/2 + cof(D)/3, with J - 1 = Q : D
+  T Qm[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      Qm[i][k] = (i == k ? T(1) + T(0.5) * trD : T(0)) - T(0.5) * D[k][i] + c[i][k] * T(1.0 / 3.0);
+  T x = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x += Qm[i][k] * D[i][k];
+  const T J = T(1) + x;
+  if (!(J > T(0))) return false;
+  // G = F^{-T} = cof(F) / J; cof(I + D) = cof(D) + (trD I - D^T) + I
+  const T Jinv = T(1) / J;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      s.G[i][k] = (c[i][k] + (i == k ? T(1) + trD : T(0)) - D[k][i]) * Jinv;
+  if (MODEL == kNH) {
+    const T mu = T(mp[0]), lam = T(mp[1]);
+    s.a = mu;
+    const T f = lam * log_ratio(x);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s.W[i][k] = f * Qm[i][k];
+  } else {   // Yeoh
+    const T C10 = T(mp[0]), C20 = T(mp[1]), C30 = T(mp[2]), D1 = T(mp[3]);
+    const T Jm23 = ep_exp(T(-2.0 / 3.0) * ep_log1p(x));
+    T I1 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const T Fik = D[i][k] + (i == k ? T(1) : T(0));
+        I1 += Fik * Fik;
+      }
+    const T z = I1 * Jm23 - T(3);
+    const T a = T(2) * Jm23 * (C10 + T(2) * C20 * z + T(3) * C30 * z * z);
+    const T beta = T(2) / D1 * J;
+    s.a = a;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        s.W[i][k] = -(a * T(1.0 / 3.0)) * ((i == k ? T(2) : T(0)) + D[i][k]) + beta * Qm[i][k];
+  }
+  return true;
+}
+
+// S += w * [a (X + G X^T) + (W : X) G]
+template <typename T>
+__device__ __forceinline__ void secant_apply(const Secant<T>& s, T w, const T (&X)[3][3], T (&S)[3][3]) {
+  T wx = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) wx += s.W[i][k] * X[i][k];
+  const T aw = w * s.a, bw = w * wx;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T gxt = s.G[i][0] * X[k][0] + s.G[i][1] * X[k][1] + s.G[i][2] * X[k][2];
+      S[i][k] += aw * (X[i][k] + gxt) + bw * s.G[i][k];
+    }
+}
+
+// Lame constants of the linear material (E, nu) or of the rest-state tangent.
+__device__ __forceinline__ void rest_lame(int model, const double* mp, double& lam, double& mu) {
+  if (model == kLinear) {
+    const double E = mp[0], nu = mp[1];
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    mu = E / (2.0 * (1.0 + nu));
+  } else if (model == kNH) {
+    mu = mp[0];
+    lam = mp[1];
+  } else {
+    mu = 2.0 * mp[0];
+    lam = 2.0 / mp[3] - 2.0 * mu / 3.0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Element force of one element: f_e = sum_q w detJ S(grad x) . grad N, S the (secant)
+// stress of the material at the operator's linearisation points.
+//   x_a = src[dof] * srcscale (* mih[dof] when scale_mih)
+// ---------------------------------------------------------------------------------------
+template <typename T, int MODEL>
+__device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int e, const double* src,
+                                           double srcscale, bool scale_mih, T (&f)[8][3]) {
+  int nd[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+  T x[8][3];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t d = (size_t)nd[a] * 3 + i;
+      double v = src[d] * srcscale;
+      if (scale_mih) v *= M.mih[d];
+      x[a][i] = T(v);
+      f[a][i] = T(0);
+    }
+  const int nsets = (MODEL == kLinear) ? 0 : op.nsets;
+  T u0[8][3], u1[8][3];
+  if (nsets >= 1) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) u0[a][i] = T(op.ulin[0][(size_t)nd[a] * 3 + i]);
+  }
+  if (nsets >= 2) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) u1[a][i] = T(op.ulin[1][(size_t)nd[a] * 3 + i]);
+  }
+  double lam_d, mu_d;
+  rest_lame(M.model, M.mp, lam_d, mu_d);
+  const T lam = T(lam_d), mu = T(mu_d);
+  bool ok = true;
+  for (int q = 0; q < 8; ++q) {
+    const QFactors<T> Q(q);
+    T Jinv[9], wdet;
+    const size_t gi = (M.congruent ? (size_t)q : (size_t)e * 8 + q) * 10;
+    if (sizeof(T) == 8) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo[gi + k]);
+      wdet = T(M.geo[gi + 9]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo32[gi + k]);
+      wdet = T(M.geo32[gi + 9]);
+    }
+    T X[3][3];
+    grad_at(Q, x, Jinv, X);
+    T S[3][3];
+    if (nsets == 0) {
+      const T tr = X[0][0] + X[1][1] + X[2][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S[i][k] = mu * (X[i][k] + X[k][i]) + (i == k ? lam * tr : T(0));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S[i][k] = T(0);
+      if (MODEL != kLinear) {
+        T Du[3][3];
+        Secant<T> sc;
+        grad_at(Q, u0, Jinv, Du);
+        ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
+        secant_apply(sc, T(op.wts[0]), X, S);
+        if (nsets >= 2) {
+          grad_at(Q, u1, Jinv, Du);
+          ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
+          secant_apply(sc, T(op.wts[1]), X, S);
+        }
+      }
+    }
+    scatter_at(Q, S, Jinv, wdet, f);
+  }
+  return ok;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_force(const Mesh& M, int e, const T (&f)[8][3], T* F) {
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[((size_t)a * M.n_elems + e) * 3 + i] = f[a][i];
+}
+
+// sum of element-slot forces of DOF 3*A + c over the elements around node A
+template <typename T>
+__device__ __forceinline__ double gather_force(const Mesh& M, const T* F, int A, int c) {
+  double s = 0.0;
+  const int p1 = M.inc_ptr[A + 1];
+  for (int p = M.inc_ptr[A]; p < p1; ++p) s += double(F[(size_t)M.inc[p] * 3 + c]);
+  return s;
+}
+
+// load scale(t): piecewise linear through the knots, constant outside
+__device__ __forceinline__ double load_scale(const Mesh& M, double t) {
+  const int n = M.n_knots;
+  if (n <= 0) return 0.0;
+  const double* kt = M.knots;
+  const double* ks = M.knots + n;
+  if (t <= kt[0]) return ks[0];
+  if (t >= kt[n - 1]) return ks[n - 1];
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (kt[mid] <= t) lo = mid; else hi = mid;
+  }
+  const double th = (t - kt[lo]) / (kt[hi] - kt[lo]);
+  return ks[lo] + th * (ks[hi] - ks[lo]);
+}
+
+// ---------------------------------------------------------------------------------------
+// Reductions (wave64 butterflies give every lane the same bits) and team synchronisation.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup, same value in every thread; red: >= 16 doubles of LDS.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  return s;
+}
+
+// A team of G co-resident workgroups (cooperative launch) synchronised through device
+// memory; G == 1 degenerates to the workgroup barrier.  Waits are bounded: a timeout sets
+// the sticky error and marks the team dead so that every workgroup leaves the kernel.
+struct GridTeam {
+  int G, rank;
+  unsigned long long* bar;
+  int* err;
+  double* slots;
+  unsigned long long gen;
+  int parity;
+  bool dead;
+
+  __device__ bool sync(int* lds_flag) {
+    __syncthreads();
+    if (G == 1) return true;
+    if (threadIdx.x == 0) {
+      gen += 1;
+      const unsigned long long target = gen * (unsigned long long)G;
+      __threadfence();
+      atomicAdd(bar, 1ull);
+      unsigned long long spins = 0;
+      int ok = 1;
+      while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1ull << 26)) {
+          ok = 0;
+          atomicCAS(err, 0, kErrDevice);
+          break;
+        }
+      }
+      __threadfence();
+      *lds_flag = ok;
+    } else {
+      gen += 1;
+    }
+    __syncthreads();
+    const bool ok = *lds_flag != 0;
+    if (!ok) dead = true;
+    return ok;
+  }
+
+  // all-reduce of one double per workgroup; fixed summation order on every workgroup
+  __device__ double allreduce(double partial, double* red, int* lds_flag) {
+    const double p = block_sum(partial, red);
+    if (G == 1) return p;
+    if (threadIdx.x == 0) slots[parity * G + rank] = p;
+    if (!sync(lds_flag)) return 0.0;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) v += slots[parity * G + i];
+    parity ^= 1;
+    return block_sum(v, red);
+  }
+};
+
+}  // namespace ep

@@ -1,0 +1,490 @@
+// HIP kernels of the exponential propagator for gfx950 and their host launch wrappers.
+#include "ep_kernels.hpp"
+#include "ep_krylov.hpp"
+
+namespace ep {
+
+// ---------------------------------------------------------------------------------------
+// setup (Sec. 2.2): element geometry at the Gauss points and at the vertices
+// ---------------------------------------------------------------------------------------
+// J[i][j] = sum_a X_a,i dN_a/dxi_j at local point xi = g * (signs of node q)
+__device__ __forceinline__ double jac_at(const double (&X)[8][3], int q, double g, double (&J)[3][3]) {
+  const int sq[3] = {node_sx(q), node_sy(q), node_sz(q)};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) J[i][j] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int s[3] = {node_sx(a), node_sy(a), node_sz(a)};
+    double fac[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fac[d] = 1.0 + g * double(s[d] * sq[d]);
+    const double dN[3] = {0.125 * s[0] * fac[1] * fac[2], 0.125 * s[1] * fac[0] * fac[2],
+                          0.125 * s[2] * fac[0] * fac[1]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) J[i][j] += X[a][i] * dN[j];
+  }
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+__global__ void k_geometry(const double* __restrict__ xyz, const int* __restrict__ conn, int n_e,
+                           double* __restrict__ geo, float* __restrict__ geo32, double* __restrict__ vdet,
+                           int* __restrict__ bad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_e) return;
+  double X[8][3];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int n = conn[(size_t)e * 8 + a];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) X[a][i] = xyz[(size_t)n * 3 + i];
+  }
+  bool ok = true;
+  for (int q = 0; q < 8; ++q) {
+    double J[3][3];
+    const double det = jac_at(X, q, kGauss, J);
+    ok &= det > 0.0;
+    const double id = 1.0 / det;
+    // inverse = adj(J) / det, (J^{-1})[j][k]
+    double Ji[9];
+    Ji[0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+    Ji[1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[3] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+    Ji[4] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[5] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[6] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+    Ji[7] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    const size_t o = ((size_t)e * 8 + q) * 10;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      geo[o + k] = Ji[k];
+      geo32[o + k] = float(Ji[k]);
+    }
+    geo[o + 9] = det;           // Gauss weights are 1
+    geo32[o + 9] = float(det);
+  }
+  for (int a = 0; a < 8; ++a) {
+    double J[3][3];
+    const double det = jac_at(X, a, 1.0, J);
+    ok &= det > 0.0;
+    vdet[(size_t)e * 8 + a] = det;
+  }
+  if (!ok) atomicOr(bad, 1);
+}
+
+// flag elements whose Gauss-point geometry differs from element 0's
+__global__ void k_congruence(const double* __restrict__ geo, int n_e, int* __restrict__ mismatch) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n_e * 80) return;
+  const double g0 = geo[idx % 80];
+  const double g = geo[idx];
+  if (fabs(g - g0) > 1e-13 * fabs(g0) + 1e-300) atomicOr(mismatch, 1);
+}
+
+// lumped mass by the vertex rule, M_A = rho * sum of vertex det J of the elements around A
+__global__ void k_mass(int n_nodes, int n_e, const int* __restrict__ inc_ptr, const int* __restrict__ inc,
+                       const double* __restrict__ vdet, double rho, const unsigned char* __restrict__ clamp,
+                       double* __restrict__ mih, double* __restrict__ mh) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= n_nodes) return;
+  double m = 0.0;
+  for (int p = inc_ptr[A]; p < inc_ptr[A + 1]; ++p) {
+    const int slot = inc[p];
+    const int a = slot / n_e, e = slot - a * n_e;
+    m += vdet[(size_t)e * 8 + a];
+  }
+  m *= rho;
+  const double sq = sqrt(m);
+  for (int c = 0; c < 3; ++c) {
+    const size_t d = (size_t)A * 3 + c;
+    const bool cl = clamp[d] != 0;
+    mh[d] = cl ? 0.0 : sq;
+    mih[d] = cl ? 0.0 : 1.0 / sq;
+  }
+}
+
+// consistent nodal forces of a dead traction on quad faces, 2x2 Gauss (weak-form term 3)
+__global__ void k_face_force(const double* __restrict__ xyz, const int* __restrict__ faces, int n_f, double t0x,
+                             double t0y, double t0z, double* __restrict__ ff) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_f) return;
+  double X[4][3];
+  for (int b = 0; b < 4; ++b)
+    for (int i = 0; i < 3; ++i) X[b][i] = xyz[(size_t)faces[(size_t)f * 4 + b] * 3 + i];
+  const double sb[4] = {-1, 1, 1, -1}, tb[4] = {-1, -1, 1, 1};
+  double acc[4] = {0, 0, 0, 0};
+  for (int g = 0; g < 4; ++g) {
+    const double s = kGauss * sb[g], t = kGauss * tb[g];
+    double a1[3] = {0, 0, 0}, a2[3] = {0, 0, 0};
+    for (int b = 0; b < 4; ++b) {
+      const double dNs = 0.25 * sb[b] * (1.0 + t * tb[b]);
+      const double dNt = 0.25 * tb[b] * (1.0 + s * sb[b]);
+      for (int i = 0; i < 3; ++i) {
+        a1[i] += dNs * X[b][i];
+        a2[i] += dNt * X[b][i];
+      }
+    }
+    const double cx = a1[1] * a2[2] - a1[2] * a2[1];
+    const double cy = a1[2] * a2[0] - a1[0] * a2[2];
+    const double cz = a1[0] * a2[1] - a1[1] * a2[0];
+    const double dA = sqrt(cx * cx + cy * cy + cz * cz);
+    for (int b = 0; b < 4; ++b) acc[b] += 0.25 * (1.0 + s * sb[b]) * (1.0 + t * tb[b]) * dA;
+  }
+  for (int b = 0; b < 4; ++b) {
+    ff[((size_t)f * 4 + b) * 3 + 0] = acc[b] * t0x;
+    ff[((size_t)f * 4 + b) * 3 + 1] = acc[b] * t0y;
+    ff[((size_t)f * 4 + b) * 3 + 2] = acc[b] * t0z;
+  }
+}
+
+__global__ void k_face_gather(int n_nodes, const int* __restrict__ finc_ptr, const int* __restrict__ finc,
+                              const double* __restrict__ ff, const double* __restrict__ mih, double* __restrict__ p0,
+                              double* __restrict__ p0bar) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= n_nodes) return;
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+    for (int p = finc_ptr[A]; p < finc_ptr[A + 1]; ++p) s += ff[(size_t)finc[p] * 3 + c];
+    const size_t d = (size_t)A * 3 + c;
+    p0[d] = s;
+    p0bar[d] = mih[d] * s;
+  }
+}
+
+// wbar = [M^{1/2} u; M^{1/2} v; s0; 0...]
+__global__ void k_set_state(int n3, int Lp, const double* __restrict__ mh, const double* __restrict__ u,
+                            const double* __restrict__ v, double s0, double* __restrict__ S) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= Lp) return;
+  double r = 0.0;
+  if (g < n3) r = mh[g] * u[g];
+  else if (g < 2 * n3) r = mh[g - n3] * v[g - n3];
+  else if (g == 2 * n3) r = s0;
+  S[g] = r;
+}
+
+// u = M^{-1/2} ubar, v = M^{-1/2} vbar (clamped entries 0)
+__global__ void k_get_state(int n3, const double* __restrict__ mih, const double* __restrict__ S,
+                            double* __restrict__ u, double* __restrict__ v) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n3) return;
+  if (u) u[d] = mih[d] * S[d];
+  if (v) v[d] = mih[d] * S[n3 + d];
+}
+
+__global__ void k_reset_ctrl(Ctrl* c, int full) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    c->bar = 0ull;
+    if (full) {
+      c->err = 0;
+      c->decision = 0;
+      for (int k = 0; k < 3; ++k) {
+        c->ks[k].k = 1;
+        c->ks[k].m_hint = 0;
+        c->ks[k].last_m = 0;
+        c->ks[k].last_k = 0;
+        c->ks[k].last_eps = 0.0;
+        c->ks[k].matvecs = 0;
+      }
+      c->drift = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// stage kernels: operator apply as two launches (element forces, per-DOF gather)
+// ---------------------------------------------------------------------------------------
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_elem_forces(Mesh M, OpArgs op, const double* __restrict__ src,
+                                                     double srcscale, int scale_mih, T* __restrict__ F,
+                                                     int* __restrict__ err) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= M.n_elems) return;
+  T f[8][3];
+  const bool ok = elem_force<T, MODEL>(M, op, e, src, srcscale, scale_mih != 0, f);
+  store_force(M, e, f, F);
+  if (!ok) atomicCAS(err, 0, kErrInverted);
+}
+
+template <typename T>
+__global__ void k_gather_H(Mesh M, const T* __restrict__ F, double* __restrict__ y) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= M.n3) return;
+  y[d] = gather_force(M, F, d / 3, d % 3);
+}
+
+template <typename T>
+__global__ void k_gather_A(Mesh M, const T* __restrict__ F, double tau, double t_eval,
+                           const double* __restrict__ x, double* __restrict__ y) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= M.Lp) return;
+  const int n3 = M.n3;
+  double w = 0.0;
+  if (g < n3) {
+    w = tau * x[n3 + g];
+  } else if (g < 2 * n3) {
+    const int d = g - n3;
+    const double pscale = load_scale(M, t_eval);
+    const double s = gather_force(M, F, d / 3, d % 3);
+    w = tau * (-M.mih[d] * s + x[2 * n3] * M.s_inv * pscale * M.p0bar[d]);
+  }
+  y[g] = w;
+}
+
+// exp(H) on one workgroup
+__global__ __launch_bounds__(kThreads) void k_expm(int m, const double* __restrict__ H, double* __restrict__ E,
+                                                   double* __restrict__ scr) {
+  __shared__ double red[16];
+  __shared__ int ired[16];
+  const double* R = wg_expm(H, m, m, scr, red, ired);
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) E[i] = R[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// energies (Sec. 5.2, generalised): per-block partial sums, then a fixed-order final sum
+// ---------------------------------------------------------------------------------------
+template <int MODEL>
+__device__ double psi_at(const double (&D)[3][3], const double* mp) {
+  if (MODEL == kLinear) {
+    double lam, mu;
+    rest_lame(kLinear, mp, lam, mu);
+    double e[3][3], tr = D[0][0] + D[1][1] + D[2][2], ee = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        e[i][k] = 0.5 * (D[i][k] + D[k][i]);
+        ee += e[i][k] * e[i][k];
+      }
+    return 0.5 * lam * tr * tr + mu * ee;
+  }
+  double c[3][3];
+  c[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+  c[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+  c[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+  c[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+  c[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+  c[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+  c[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+  c[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+  c[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+  const double trD = D[0][0] + D[1][1] + D[2][2];
+  double x = 0.0, I1 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) {
+      const double q = (i == k ? 1.0 + 0.5 * trD : 0.0) - 0.5 * D[k][i] + c[i][k] / 3.0;
+      x += q * D[i][k];
+      const double F = D[i][k] + (i == k ? 1.0 : 0.0);
+      I1 += F * F;
+    }
+  const double lnJ = log1p(x);
+  if (MODEL == kNH) {
+    const double mu = mp[0], lam = mp[1];
+    return 0.5 * mu * (I1 - 3.0) - mu * lnJ + 0.5 * lam * lnJ * lnJ;
+  }
+  const double z = I1 * exp(-2.0 / 3.0 * lnJ) - 3.0;
+  return mp[0] * z + mp[1] * z * z + mp[2] * z * z * z + x * x / mp[3];
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(256) void k_energy_elem(Mesh M, const double* __restrict__ S,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[16];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (e < M.n_elems) {
+    double u[8][3];
+    for (int a = 0; a < 8; ++a) {
+      const int n = M.conn[(size_t)e * 8 + a];
+      for (int i = 0; i < 3; ++i) u[a][i] = M.mih[(size_t)n * 3 + i] * S[(size_t)n * 3 + i];
+    }
+    for (int q = 0; q < 8; ++q) {
+      const QFactors<double> Qf(q);
+      const size_t gi = (M.congruent ? (size_t)q : (size_t)e * 8 + q) * 10;
+      double Jinv[9];
+      for (int k = 0; k < 9; ++k) Jinv[k] = M.geo[gi + k];
+      double D[3][3];
+      grad_at(Qf, u, Jinv, D);
+      acc += M.geo[gi + 9] * psi_at<MODEL>(D, M.mp);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_energy_vec(int n3, const double* __restrict__ S,
+                                                    const double* __restrict__ p0bar, double* __restrict__ partial) {
+  __shared__ double red[16];
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  double ke = 0.0, we = 0.0;
+  if (d < n3) {
+    const double vb = S[n3 + d];
+    ke = 0.5 * vb * vb;
+    we = p0bar[d] * S[d];
+  }
+  const double a = block_sum(ke, red);
+  const double b = block_sum(we, red);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = a;
+    partial[2 * blockIdx.x + 1] = b;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_energy_final(Mesh M, double t, const double* __restrict__ pe, int npe,
+                                                      const double* __restrict__ pv, int npv,
+                                                      double* __restrict__ out) {
+  __shared__ double red[16];
+  double se = 0.0, ke = 0.0, we = 0.0;
+  for (int i = threadIdx.x; i < npe; i += blockDim.x) se += pe[i];
+  for (int i = threadIdx.x; i < npv; i += blockDim.x) {
+    ke += pv[2 * i];
+    we += pv[2 * i + 1];
+  }
+  se = block_sum(se, red);
+  ke = block_sum(ke, red);
+  we = block_sum(we, red);
+  if (threadIdx.x == 0) {
+    out[0] = ke;
+    out[1] = se;
+    out[2] = load_scale(M, t) * we;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// persistent projection kernel: one cooperative launch per exp(tau A) w
+// ---------------------------------------------------------------------------------------
+template <typename T, int MODEL>
+__global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
+  extern __shared__ double lds[];
+  const int C = A.W.chunk;
+  double* lw = lds;
+  double* lv = lds + C;
+  double* red = lv + C;
+  double* yb = red + 16;
+  int* flag = (int*)(yb + kMaxM);
+  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, &A.W.ctrl->bar, &A.W.ctrl->err, A.W.slots, 0ull, 0, false};
+  expv_body<T, MODEL>(tm, A, lw, lv, red, yb, flag);
+}
+
+size_t expv_lds_bytes(int chunk) { return (size_t)(2 * chunk + 16 + kMaxM) * sizeof(double) + 16 * sizeof(int); }
+
+template <typename T, int MODEL>
+static const void* expv_fn() {
+  return reinterpret_cast<const void*>(&k_expv<T, MODEL>);
+}
+
+static const void* expv_kernel(int prec, int model) {
+  if (prec == 0) {
+    if (model == kLinear) return expv_fn<double, kLinear>();
+    if (model == kNH) return expv_fn<double, kNH>();
+    return expv_fn<double, kYeoh>();
+  }
+  if (model == kLinear) return expv_fn<float, kLinear>();
+  if (model == kNH) return expv_fn<float, kNH>();
+  return expv_fn<float, kYeoh>();
+}
+
+hipError_t expv_max_blocks(int prec, int model, int chunk, int* blocks_per_cu) {
+  const void* fn = expv_kernel(prec, model);
+  const size_t lds = expv_lds_bytes(chunk);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds);
+}
+
+hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
+  k_reset_ctrl<<<1, 1, 0, st>>>(a.W.ctrl, 0);
+  const void* fn = expv_kernel(prec, a.M.model);
+  const size_t lds = expv_lds_bytes(a.W.chunk);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  ExpvArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel(fn, dim3(a.W.G), dim3(kThreads), args, (unsigned)lds, st);
+}
+
+// ---------------------------------------------------------------------------------------
+// host wrappers of the small kernels
+// ---------------------------------------------------------------------------------------
+static inline int nblk(long long n, int b) { return (int)((n + b - 1) / b); }
+
+void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,
+                     hipStream_t st) {
+  if (n_e > 0) k_geometry<<<nblk(n_e, 128), 128, 0, st>>>(xyz, conn, n_e, geo, geo32, vdet, bad);
+}
+void launch_congruence(const double* geo, int n_e, int* mismatch, hipStream_t st) {
+  if (n_e > 0) k_congruence<<<nblk((long long)n_e * 80, 256), 256, 0, st>>>(geo, n_e, mismatch);
+}
+void launch_mass(int n_nodes, int n_e, const int* inc_ptr, const int* inc, const double* vdet, double rho,
+                 const unsigned char* clamp, double* mih, double* mh, hipStream_t st) {
+  if (n_nodes > 0) k_mass<<<nblk(n_nodes, 256), 256, 0, st>>>(n_nodes, n_e, inc_ptr, inc, vdet, rho, clamp, mih, mh);
+}
+void launch_faces(const double* xyz, const int* faces, int n_f, const double* t0, double* ff, int n_nodes,
+                  const int* finc_ptr, const int* finc, const double* mih, double* p0, double* p0bar, hipStream_t st) {
+  if (n_f > 0) k_face_force<<<nblk(n_f, 128), 128, 0, st>>>(xyz, faces, n_f, t0[0], t0[1], t0[2], ff);
+  if (n_nodes > 0) k_face_gather<<<nblk(n_nodes, 256), 256, 0, st>>>(n_nodes, finc_ptr, finc, ff, mih, p0, p0bar);
+}
+void launch_set_state(int n3, int Lp, const double* mh, const double* u, const double* v, double s0, double* S,
+                      hipStream_t st) {
+  k_set_state<<<nblk(Lp, 256), 256, 0, st>>>(n3, Lp, mh, u, v, s0, S);
+}
+void launch_get_state(int n3, const double* mih, const double* S, double* u, double* v, hipStream_t st) {
+  k_get_state<<<nblk(n3, 256), 256, 0, st>>>(n3, mih, S, u, v);
+}
+void launch_reset_ctrl(Ctrl* c, hipStream_t st) { k_reset_ctrl<<<1, 1, 0, st>>>(c, 1); }
+
+template <typename T>
+static void elem_forces_t(const Mesh& M, const OpArgs& op, const double* src, double sc, int scale_mih, T* F, int* err,
+                          hipStream_t st) {
+  const int nb = nblk(M.n_elems, 256);
+  if (M.n_elems == 0) return;
+  if (M.model == kLinear) k_elem_forces<T, kLinear><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+  else if (M.model == kNH) k_elem_forces<T, kNH><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+  else k_elem_forces<T, kYeoh><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+}
+
+void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
+                    int* err, hipStream_t st) {
+  if (prec == 0) {
+    elem_forces_t<double>(M, op, x, 1.0, 0, F, err, st);
+    k_gather_H<double><<<nblk(M.n3, 256), 256, 0, st>>>(M, F, y);
+  } else {
+    elem_forces_t<float>(M, op, x, 1.0, 0, F32, err, st);
+    k_gather_H<float><<<nblk(M.n3, 256), 256, 0, st>>>(M, F32, y);
+  }
+}
+
+void launch_apply_A(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
+                    int* err, hipStream_t st) {
+  if (prec == 0) {
+    elem_forces_t<double>(M, op, x, 1.0, 1, F, err, st);
+    k_gather_A<double><<<nblk(M.Lp, 256), 256, 0, st>>>(M, F, op.tau, op.t_eval, x, y);
+  } else {
+    elem_forces_t<float>(M, op, x, 1.0, 1, F32, err, st);
+    k_gather_A<float><<<nblk(M.Lp, 256), 256, 0, st>>>(M, F32, op.tau, op.t_eval, x, y);
+  }
+}
+
+void launch_expm(int m, const double* H, double* E, double* scr, hipStream_t st) {
+  k_expm<<<1, kThreads, 0, st>>>(m, H, E, scr);
+}
+
+int energy_blocks(const Mesh& M) { return nblk(M.n_elems, 256); }
+int energy_vec_blocks(const Mesh& M) { return nblk(M.n3, 256); }
+
+void launch_energy(const Mesh& M, const double* S, double t, double* pe, double* pv, double* out, hipStream_t st) {
+  const int ne = energy_blocks(M), nv = energy_vec_blocks(M);
+  if (ne > 0) {
+    if (M.model == kLinear) k_energy_elem<kLinear><<<ne, 256, 0, st>>>(M, S, pe);
+    else if (M.model == kNH) k_energy_elem<kNH><<<ne, 256, 0, st>>>(M, S, pe);
+    else k_energy_elem<kYeoh><<<ne, 256, 0, st>>>(M, S, pe);
+  }
+  if (nv > 0) k_energy_vec<<<nv, 256, 0, st>>>(M.n3, S, M.p0bar, pv);
+  k_energy_final<<<1, 256, 0, st>>>(M, t, pe, ne, pv, nv, out);
+}
+
+}  // namespace ep

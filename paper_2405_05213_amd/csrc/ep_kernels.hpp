@@ -1,0 +1,32 @@
+// Host-side launch wrappers of the kernels in ep_kernels.hip / ep_batch.hip.
+#pragma once
+
+#include "ep_common.hpp"
+
+namespace ep {
+
+size_t expv_lds_bytes(int chunk);
+hipError_t expv_max_blocks(int prec, int model, int chunk, int* blocks_per_cu);
+hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
+
+void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,
+                     hipStream_t st);
+void launch_congruence(const double* geo, int n_e, int* mismatch, hipStream_t st);
+void launch_mass(int n_nodes, int n_e, const int* inc_ptr, const int* inc, const double* vdet, double rho,
+                 const unsigned char* clamp, double* mih, double* mh, hipStream_t st);
+void launch_faces(const double* xyz, const int* faces, int n_f, const double* t0, double* ff, int n_nodes,
+                  const int* finc_ptr, const int* finc, const double* mih, double* p0, double* p0bar, hipStream_t st);
+void launch_set_state(int n3, int Lp, const double* mh, const double* u, const double* v, double s0, double* S,
+                      hipStream_t st);
+void launch_get_state(int n3, const double* mih, const double* S, double* u, double* v, hipStream_t st);
+void launch_reset_ctrl(Ctrl* c, hipStream_t st);
+void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
+                    int* err, hipStream_t st);
+void launch_apply_A(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
+                    int* err, hipStream_t st);
+void launch_expm(int m, const double* H, double* E, double* scr, hipStream_t st);
+int energy_blocks(const Mesh& M);
+int energy_vec_blocks(const Mesh& M);
+void launch_energy(const Mesh& M, const double* S, double t, double* pe, double* pv, double* out, hipStream_t st);
+
+}  // namespace ep

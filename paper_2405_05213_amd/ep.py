@@ -1,0 +1,258 @@
+"""Thin ctypes binding of libep.so (include/ep.h).
+
+Argument marshalling only: every numerical step runs in the HIP library.  PyTorch is
+used for device memory (the workspace and device vectors) and the stream.
+Importing works without a GPU; calls that need the library raise if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libep.so")
+
+EP_OK, EP_ERR_ARG, EP_ERR_ORDER, EP_ERR_HIP, EP_ERR_KRYLOV = 0, -1, -2, -3, -4
+EP_ERR_INVERTED, EP_ERR_NONFINITE, EP_ERR_WORKSPACE, EP_ERR_DEVICE = -5, -6, -7, -8
+MODELS = {"linear": 0, "nh": 1, "yeoh": 2}
+PRECISIONS = {"f64": 0, "mixed_f32": 1}
+
+_i64, _i32, _dbl, _vp = C.c_int64, C.c_int32, C.c_double, C.c_void_p
+_P = C.POINTER
+
+
+class EPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"ep error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_SIGS = {
+    "ep_create": [_P(_vp), C.c_int],
+    "ep_destroy": [_vp],
+    "ep_last_error": [_vp],
+    "ep_version": [],
+    "ep_set_stream": [_vp, _vp],
+    "ep_set_mesh_hex8": [_vp, _i64, _vp, _i64, _vp],
+    "ep_set_material": [_vp, C.c_int, _vp, C.c_int, _dbl],
+    "ep_set_dirichlet": [_vp, _i64, _vp],
+    "ep_set_traction": [_vp, _i64, _vp, _vp, _i64, _vp, _vp],
+    "ep_set_krylov": [_vp, _dbl, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dbl],
+    "ep_set_precision": [_vp, C.c_int],
+    "ep_set_launch": [_vp, C.c_int],
+    "ep_workspace_size": [_vp, _P(C.c_size_t)],
+    "ep_bind_workspace": [_vp, _vp, C.c_size_t],
+    "ep_set_state": [_vp, _dbl, _vp, _vp],
+    "ep_step": [_vp, _dbl, _i64],
+    "ep_sync": [_vp],
+    "ep_get_state": [_vp, _P(_dbl), _vp, _vp],
+    "ep_get_energy": [_vp, _P(_dbl), _P(_dbl), _P(_dbl)],
+    "ep_get_stats": [_vp, _P(_i64), _P(C.c_int), _P(_dbl), _P(C.c_int), _P(_dbl)],
+    "ep_get_step_log": [_vp, C.c_int, _vp, _vp, _vp, _vp],
+    "ep_apply_H": [_vp, _vp, _vp, _vp],
+    "ep_apply_A": [_vp, _vp, _dbl, _dbl, _vp, _vp],
+    "ep_vector_length": [_vp, _P(_i64), _P(_i64)],
+    "ep_expm": [_vp, C.c_int, _vp, _vp],
+    "ep_arnoldi": [_vp, _vp, _dbl, _dbl, _vp, C.c_int, _vp, _vp, _P(C.c_int)],
+    "ep_expv": [_vp, _vp, _dbl, _dbl, _vp, _vp, _P(C.c_int), _P(C.c_int), _P(_dbl)],
+    "ep_batch_add_instance": [_vp, _i64, _vp, _i64, _vp, C.c_int, _vp, C.c_int, _dbl, _i64, _vp, _i64, _vp,
+                              _vp, _i64, _vp, _vp, _P(_i32)],
+    "ep_batch_set_state": [_vp, _i32, _dbl, _vp, _vp],
+    "ep_batch_step": [_vp, _dbl, _i64],
+    "ep_batch_get_state": [_vp, _i32, _P(_dbl), _vp, _vp],
+    "ep_batch_get_stats": [_vp, _i32, _P(_i64), _P(C.c_int), _P(C.c_int), _P(_dbl)],
+}
+EXPORTED = sorted(_SIGS)
+
+
+def lib():
+    """Load libep.so; raises (loudly) if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2405_05213_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_char_p if name in ("ep_last_error", "ep_version") else C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    """Host numpy array or torch tensor -> void pointer (None stays None)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32a(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+class Context:
+    """One ep_ctx.  device=-1 gives a host-only context (validation only)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._L = lib()
+        h = C.c_void_p()
+        rc = self._L.ep_create(C.byref(h), device)
+        if rc != EP_OK:
+            raise EPError(rc, f"ep_create(device={device}) failed")
+        self.h = h
+        self.device = device
+        self.workspace = None
+        if stream is not None:
+            self._call("ep_set_stream", C.c_void_p(stream))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and getattr(self, "_L", None) is not None:
+            self._L.ep_destroy(h)
+            self.h = None
+
+    def _call(self, name, *args):
+        rc = getattr(self._L, name)(self.h, *args)
+        if rc != EP_OK:
+            msg = self._L.ep_last_error(self.h)
+            raise EPError(rc, msg.decode() if msg else name)
+        return rc
+
+    # ---------------------------------------------------------------- setup
+    def set_mesh(self, xyz, conn):
+        self._xyz, self._conn = _f64(xyz), _i32a(conn)
+        self._call("ep_set_mesh_hex8", self._xyz.shape[0], _ptr(self._xyz), self._conn.shape[0], _ptr(self._conn))
+        self.n_nodes = self._xyz.shape[0]
+
+    def set_material(self, model: str, params, rho: float):
+        p = _f64(params)
+        self._call("ep_set_material", MODELS[model], _ptr(p), p.size, float(rho))
+
+    def set_dirichlet(self, dofs):
+        d = _i32a(dofs)
+        self._call("ep_set_dirichlet", d.size, _ptr(d))
+
+    def set_traction(self, faces, t0, knots_t, knots_s):
+        f = _i32a(faces).reshape(-1, 4)
+        t = _f64(t0)
+        kt, ks = _f64(knots_t), _f64(knots_s)
+        self._call("ep_set_traction", f.shape[0], _ptr(f), _ptr(t), kt.size, _ptr(kt), _ptr(ks))
+
+    def set_krylov(self, tol=1e-10, m_max=64, check_every=4, m_fixed=0, k_fixed=0, max_substeps=64, s0=-1.0):
+        self._call("ep_set_krylov", float(tol), int(m_max), int(check_every), int(m_fixed), int(k_fixed),
+                   int(max_substeps), float(s0))
+
+    def set_precision(self, prec: str):
+        self._call("ep_set_precision", PRECISIONS[prec])
+
+    def set_launch(self, workgroups: int):
+        self._call("ep_set_launch", int(workgroups))
+
+    def workspace_size(self) -> int:
+        n = C.c_size_t()
+        self._call("ep_workspace_size", C.byref(n))
+        return n.value
+
+    def bind(self):
+        import torch
+        n = self.workspace_size()
+        self.workspace = torch.empty(n + 256, dtype=torch.uint8, device=f"cuda:{self.device}")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._call("ep_bind_workspace", C.c_void_p(base + off), n)
+
+    # ---------------------------------------------------------------- state
+    def set_state(self, t, u, v):
+        u, v = _f64(u), _f64(v)
+        self._call("ep_set_state", float(t), _ptr(u), _ptr(v))
+
+    def step(self, dt, n_steps=1):
+        self._call("ep_step", float(dt), int(n_steps))
+
+    def sync(self):
+        self._call("ep_sync")
+
+    def get_state(self):
+        t = C.c_double()
+        u = np.empty(3 * self.n_nodes)
+        v = np.empty(3 * self.n_nodes)
+        self._call("ep_get_state", C.byref(t), _ptr(u), _ptr(v))
+        return t.value, u, v
+
+    def energy(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        self._call("ep_get_energy", C.byref(a), C.byref(b), C.byref(c))
+        return a.value, b.value, c.value
+
+    def stats(self):
+        mv, m, k = C.c_int64(), C.c_int(), C.c_int()
+        eps, dr = C.c_double(), C.c_double()
+        self._call("ep_get_stats", C.byref(mv), C.byref(m), C.byref(eps), C.byref(k), C.byref(dr))
+        return {"matvecs": mv.value, "m": m.value, "eps": eps.value, "k": k.value, "drift": dr.value}
+
+    def step_log(self, n):
+        mc, mp, kc = (np.zeros(n, np.int32) for _ in range(3))
+        ec = np.zeros(n)
+        self._call("ep_get_step_log", int(n), _ptr(mc), _ptr(mp), _ptr(kc), _ptr(ec))
+        return {"m_corr": mc, "m_pred": mp, "k_corr": kc, "eps_corr": ec}
+
+    # ---------------------------------------------------------------- stages (device tensors)
+    def vector_length(self):
+        a, b = C.c_int64(), C.c_int64()
+        self._call("ep_vector_length", C.byref(a), C.byref(b))
+        return a.value, b.value
+
+    def apply_H(self, u_lin, x, y):
+        self._call("ep_apply_H", _ptr(u_lin), _ptr(x), _ptr(y))
+
+    def apply_A(self, u_lin, tau, pscale, x, y):
+        self._call("ep_apply_A", _ptr(u_lin), float(tau), float(pscale), _ptr(x), _ptr(y))
+
+    def expm(self, H):
+        H = _f64(H)
+        m = H.shape[0]
+        E = np.empty((m, m))
+        self._call("ep_expm", int(m), _ptr(H), _ptr(E))
+        return E
+
+    def arnoldi(self, u_lin, tau, pscale, w, m, V=None):
+        H = np.zeros((m + 1, m))
+        steps = C.c_int()
+        self._call("ep_arnoldi", _ptr(u_lin), float(tau), float(pscale), _ptr(w), int(m), _ptr(V), _ptr(H),
+                   C.byref(steps))
+        return H, steps.value
+
+    def expv(self, u_lin, tau, pscale, w, y):
+        m, k, e = C.c_int(), C.c_int(), C.c_double()
+        self._call("ep_expv", _ptr(u_lin), float(tau), float(pscale), _ptr(w), _ptr(y), C.byref(m), C.byref(k),
+                   C.byref(e))
+        return m.value, k.value, e.value
+
+
+def solver_from_problem(prob, device=0, tol=None, m_max=64, check_every=4, m_fixed=0, k_fixed=0,
+                        max_substeps=64, s0=-1.0, precision="f64", workgroups=0, stream=None):
+    """Context set up from a workloads.Problem, bound and at the problem's initial state."""
+    ctx = Context(device, stream=stream)
+    ctx.set_mesh(prob.xyz, prob.conn)
+    ctx.set_material(prob.model, prob.params, prob.rho)
+    if len(prob.clamped):
+        ctx.set_dirichlet(prob.clamped)
+    if len(prob.faces):
+        ctx.set_traction(prob.faces, prob.t0, prob.knots_t, prob.knots_s)
+    ctx.set_krylov(prob.tol if tol is None else tol, m_max, check_every, m_fixed, k_fixed, max_substeps, s0)
+    ctx.set_precision(precision)
+    ctx.set_launch(workgroups)
+    ctx.bind()
+    ctx.set_state(0.0, prob.u0, prob.v0)
+    return ctx

@@ -1,0 +1,42 @@
+"""Helpers shared by the GPU parity tests: building a HIP context and an oracle propagator
+from the same seeded workload, and mapping between their vector layouts."""
+import sys
+
+import numpy as np
+
+from paper_2405_05213_amd import ep as epmod
+from oracle.stepper import Propagator
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(prob, **kw):
+    """(HIP context, oracle propagator) for one problem with the same Krylov settings."""
+    okw = {k: kw[k] for k in ("tol", "m_max", "check_every", "m_fixed", "k_fixed", "max_substeps") if k in kw}
+    if "s0" in kw and kw["s0"] >= 0:
+        okw["s0"] = kw["s0"]
+    ctx = epmod.solver_from_problem(prob, **kw)
+    orc = Propagator(prob, **okw)
+    return ctx, orc
+
+
+def to_gpu_vec(orc, w_free, Lp):
+    """Oracle augmented vector (free DOFs) -> library layout [ubar | vbar | s | 0 pad]."""
+    n3, N = orc.n3, orc.N
+    out = np.zeros(Lp)
+    out[orc.free] = w_free[:N]
+    out[n3 + orc.free] = w_free[N:2 * N]
+    out[2 * n3] = w_free[2 * N]
+    return out
+
+
+def from_gpu_vec(orc, x):
+    n3, N = orc.n3, orc.N
+    return np.concatenate([x[orc.free], x[n3 + orc.free], [x[2 * n3]]])
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))

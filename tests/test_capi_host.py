@@ -1,0 +1,89 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol, and
+validates arguments / call order on a host-only context (no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2405_05213_amd import ep as epmod
+from workloads import config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ep.h")).read()
+    return sorted(set(re.findall(r"^(?:ep_status|const char\*)\s+(ep_\w+)\(", src, flags=re.M)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == epmod.EXPORTED
+
+
+def test_library_exports_every_declared_symbol():
+    L = epmod.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.ep_version()
+
+
+def _host_ctx():
+    return epmod.Context(device=-1)
+
+
+def test_validation_errors():
+    c = _host_ctx()
+    p = config("c1")
+    with pytest.raises(epmod.EPError) as e:
+        c.set_mesh(p.xyz, p.conn + 1000)
+    assert e.value.code == epmod.EP_ERR_ARG
+    c.set_mesh(p.xyz, p.conn)
+    with pytest.raises(epmod.EPError) as e:
+        c.set_material("linear", (200e9, 0.7), 7800.0)
+    assert e.value.code == epmod.EP_ERR_ARG
+    with pytest.raises(epmod.EPError):
+        c.set_material("yeoh", (1.0, 0.0, 0.0), 1000.0)
+    with pytest.raises(epmod.EPError):
+        c.set_dirichlet([3 * p.n_nodes])
+    with pytest.raises(epmod.EPError):
+        c.set_traction(p.faces, p.t0, [0.0, 0.0], [1.0, 2.0])       # knots not ascending
+    with pytest.raises(epmod.EPError):
+        c.set_krylov(m_max=300)
+    with pytest.raises(epmod.EPError):
+        c.set_krylov(m_fixed=70, m_max=64)
+    # order: state / step before binding
+    with pytest.raises(epmod.EPError) as e:
+        c.step(1e-4)
+    assert e.value.code == epmod.EP_ERR_ORDER
+    with pytest.raises(epmod.EPError) as e:
+        c.workspace_size()                     # material missing
+    assert e.value.code == epmod.EP_ERR_ORDER
+    c.set_material("linear", (200e9, 0.3), 7800.0)
+    assert c.workspace_size() > 0
+
+
+def test_workspace_size_scales_with_subspace():
+    p = config("c1")
+    sizes = []
+    for m in (16, 64):
+        c = _host_ctx()
+        c.set_mesh(p.xyz, p.conn)
+        c.set_material("linear", (200e9, 0.3), 7800.0)
+        c.set_krylov(m_max=m)
+        sizes.append(c.workspace_size())
+    assert sizes[1] > sizes[0]
+
+
+def test_host_context_cannot_bind():
+    L = epmod.lib()
+    c = _host_ctx()
+    p = config("c1")
+    c.set_mesh(p.xyz, p.conn)
+    c.set_material("linear", (200e9, 0.3), 7800.0)
+    n = c.workspace_size()
+    rc = L.ep_bind_workspace(c.h, C.c_void_p(256), n)
+    assert rc == epmod.EP_ERR_HIP
+    rc = L.ep_bind_workspace(c.h, C.c_void_p(257), n)
+    assert rc == epmod.EP_ERR_WORKSPACE

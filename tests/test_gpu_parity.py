@@ -1,0 +1,148 @@
+"""HIP path vs the CPU oracle, element by element, on seeded workloads (needs an MI355X)."""
+import numpy as np
+import pytest
+
+from workloads import config, distort
+from oracle import krylov
+from tests.gpu_util import from_gpu_vec, pair, rel, say, to_gpu_vec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+CASES_H = [
+    ("linear", "c1", {}, False),
+    ("linear", "c1", {}, True),
+    ("nh", "c3", dict(nx=8, ny=2, nz=2), False),
+    ("nh", "c3", dict(nx=8, ny=2, nz=2), True),
+    ("yeoh", "c4", dict(nx=4, ny=3, nz=3), True),
+]
+
+
+@pytest.mark.parametrize("model,name,over,distorted", CASES_H)
+@pytest.mark.parametrize("prec", ["f64", "mixed_f32"])
+def test_apply_H_matches_oracle(model, name, over, distorted, prec):
+    """Operator apply (weak-form term 2 with the secant split): y = H(u) x on all DOFs."""
+    say(f"[apply_H] {model} {name} {over} distorted={distorted} prec={prec}")
+    p = config(name, **over)
+    if distorted:
+        p = distort(p, 0.2, seed=5)
+    ctx, orc = pair(p, precision=prec)
+    rng = np.random.default_rng(3)
+    n3 = 3 * p.n_nodes
+    x = rng.normal(size=n3)
+    u = None if model == "linear" else 0.03 * rng.normal(size=n3) * (p.xyz.max() - p.xyz.min())
+    y = torch.zeros(n3, dtype=torch.float64, device=DEV)
+    ctx.apply_H(None if u is None else _t(u), _t(x), y)
+    ref = orc.fem.H_apply(u, x)
+    tol = 1e-12 if prec == "f64" else 2e-6
+    assert rel(_np(y), ref) < tol
+
+
+@pytest.mark.parametrize("m,scale", [(1, 0.3), (6, 0.9), (12, 3.0), (30, 40.0), (64, 250.0), (128, 900.0)])
+def test_expm_matches_oracle(m, scale):
+    say(f"[expm] m={m} scale={scale}")
+    p = config("c1")
+    ctx, _ = pair(p, m_max=128)
+    rng = np.random.default_rng(m)
+    H = np.triu(rng.normal(size=(m, m)), -1)
+    H *= scale / krylov.norm1(H)
+    E = ctx.expm(H)
+    R = krylov.expm(H)
+    assert np.abs(E - R).max() <= 1e-13 * max(1.0, np.abs(R).max()) * max(1.0, scale / 10)
+
+
+@pytest.mark.parametrize("name,over,workgroups", [("c1", {}, 1), ("c1", {}, 4), ("c2", dict(nx=20, ny=4, nz=4), 0)])
+def test_arnoldi_matches_oracle(name, over, workgroups):
+    """Arnoldi-MGS: same Hessenberg matrix and basis as the oracle on the same operator."""
+    say(f"[arnoldi] {name} {over} G={workgroups}")
+    p = config(name, **over)
+    ctx, orc = pair(p, m_max=40, workgroups=workgroups)
+    rng = np.random.default_rng(7)
+    N = orc.N
+    w = np.concatenate([orc.Mh * rng.normal(0, 1e-5, N), orc.Mh * rng.normal(0, 1e-2, N), [1.0]])
+    L, Lp = ctx.vector_length()
+    wg = _t(to_gpu_vec(orc, w, Lp))
+    m = 30
+    V = torch.zeros((m + 1) * Lp, dtype=torch.float64, device=DEV)
+    dt = 1e-4
+    H, steps = ctx.arnoldi(None, dt, 1.0, wg, m, V)
+    assert steps == m
+    pbar = orc.P0bar
+    Vo, Ho, beta, so = krylov.arnoldi_mgs(lambda v: orc.A_apply(v, dt, None, pbar), w, m)
+    assert so == m
+    scale = np.abs(Ho).max()
+    assert np.abs(H - Ho).max() <= 1e-9 * scale
+    Vg = _np(V).reshape(m + 1, Lp)
+    for j in (0, 1, 5, m):
+        assert rel(from_gpu_vec(orc, Vg[j]), Vo[j]) < 1e-8
+
+
+@pytest.mark.parametrize("dt,workgroups", [(2e-5, 1), (1e-4, 2), (4e-4, 3)])
+def test_expv_matches_oracle(dt, workgroups):
+    say(f"[expv] c1 dt={dt} G={workgroups}")
+    p = config("c1")
+    ctx, orc = pair(p, m_max=48, workgroups=workgroups)
+    rng = np.random.default_rng(11)
+    N = orc.N
+    w = np.concatenate([orc.Mh * rng.normal(0, 1e-5, N), orc.Mh * rng.normal(0, 1e-2, N), [1.0]])
+    L, Lp = ctx.vector_length()
+    y = torch.zeros(Lp, dtype=torch.float64, device=DEV)
+    m, k, eps = ctx.expv(None, dt, 1.0, _t(to_gpu_vec(orc, w, Lp)), y)
+    yo, info = krylov.expv(lambda v, f: orc.A_apply(v, f, None, orc.P0bar), w, dt, tol=p.tol, m_max=48,
+                           check_every=4, state={})
+    assert k == info["k"] and m == info["m"][-1]
+    assert rel(from_gpu_vec(orc, _np(y)), yo) < 1e-9
+
+
+@pytest.mark.parametrize("mode", ["fixed", "adaptive"])
+def test_linear_steps_c1(mode):
+    """200 steps of the 10x2x2 linear cantilever (dt 1e-4, tol 1e-10) against the oracle."""
+    say(f"[steps] c1 linear {mode}")
+    p = config("c1")
+    kw = dict(m_max=64) if mode == "adaptive" else dict(m_max=64, m_fixed=32, k_fixed=1)
+    ctx, orc = pair(p, **kw)
+    ctx.step(p.dt, p.n_steps)
+    t, u, v = ctx.get_state()
+    orc.run(p.dt, p.n_steps)
+    assert abs(t - orc.t) < 1e-15
+    assert rel(u, orc.u()) < 1e-8
+    assert rel(v, orc.v()) < 1e-8
+    ke, se, we = ctx.energy()
+    ko, so_, wo = orc.energies()
+    assert abs(ke - ko) <= 1e-8 * (ko + so_) and abs(se - so_) <= 1e-8 * (ko + so_)
+    assert abs(we - wo) <= 1e-8 * abs(wo)
+    if mode == "adaptive":
+        log = ctx.step_log(p.n_steps)
+        mo = np.array([r["corr"]["m"][0] for r in orc.log])
+        assert np.array_equal(log["m_corr"], mo)
+
+
+@pytest.mark.parametrize("model,name,over", [("nh", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4)),
+                                              ("yeoh", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3))])
+@pytest.mark.parametrize("mode", ["fixed", "adaptive"])
+def test_nonlinear_steps(model, name, over, mode):
+    """Predictor-corrector steps of the Neo-Hookean / Yeoh solids against the oracle."""
+    say(f"[steps] {model} {name} {over} {mode}")
+    p = config(name, **over)
+    n = 12
+    kw = dict(m_max=48) if mode == "adaptive" else dict(m_max=48, m_fixed=24, k_fixed=1)
+    ctx, orc = pair(p, **kw)
+    ctx.step(p.dt, n)
+    t, u, v = ctx.get_state()
+    orc.run(p.dt, n)
+    assert rel(u, orc.u()) < 1e-8
+    assert rel(v, orc.v()) < 1e-8
+    ke, se, we = ctx.energy()
+    ko, so_, wo = orc.energies()
+    assert abs(se - so_) <= 1e-8 * (ko + so_ + abs(wo))
