@@ -20,6 +20,7 @@ using namespace ep;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr long long kMaxChunk = 9984;     // (2 * 9984 + 272) doubles of LDS fit in 160 KB
 
 struct Layout {
   size_t off = 0;
@@ -172,7 +173,11 @@ static void fill_traction(Inst& I, int64_t n_faces, const int32_t* fn, const dou
 // ------------------------------------------------------------------------------ layout
 static int pick_G(const ep_ctx* c, const Inst& I, int* chunk) {
   const int maxG = std::max(1, c->cus);
-  int G = c->G_user > 0 ? c->G_user : (int)std::min<long long>(maxG, std::max<long long>(1, (I.Lp + 4095) / 4096));
+  // the workgroup's slice of the Arnoldi vector (and of the previous basis vector) lives in
+  // LDS: at most kMaxChunk entries per workgroup
+  const int Gmin = (int)((I.Lp + kMaxChunk - 1) / kMaxChunk);
+  int G = c->G_user > 0 ? c->G_user : (int)std::min<long long>(maxG, std::max<long long>(1, (I.Lp + 2047) / 2048));
+  G = std::max(G, Gmin);
   G = std::max(1, std::min(G, std::min(I.Lp / 64 > 0 ? I.Lp / 64 : 1, 1024)));
   int C = (I.Lp + G - 1) / G;
   C = (C + 63) / 64 * 64;
@@ -208,7 +213,7 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_F32 = L.take(4 * 24 * ne);
   I.o_hist = L.take(8 * 3 * n3);
   I.o_stage = L.take(8 * 2 * n3);
-  I.o_slots = L.take(8 * 2 * (size_t)std::max(Gmax, 1));
+  I.o_slots = L.take(8 * 9 * (size_t)std::max(Gmax, 1));   // G barrier flags + 8 G ring slots
   I.o_H = L.take(8 * (mm + 1) * mm);
   I.o_Escr = L.take(8 * 9 * mm * mm);     // 8 m^2 expm work + m^2 output staging
   I.o_y = L.take(8 * (mm + 1));
@@ -220,9 +225,11 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_flags = L.take(4 * 4);
 }
 
+static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
+
 static size_t plan_all(ep_ctx* c) {
   Layout L;
-  const int Gmax = std::max(1, std::max(c->cus, c->G_user));
+  const int Gmax = Gmax_of(c);
   if (!c->batch) {
     plan_inst(c, c->one, L, Gmax);
   } else {
@@ -335,7 +342,8 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk) {
   W.X = dptr<double>(c, I.o_X);
   W.F = dptr<double>(c, I.o_F);
   W.F32 = dptr<float>(c, I.o_F32);
-  W.slots = dptr<double>(c, I.o_slots);
+  W.flags = dptr<unsigned long long>(c, I.o_slots);
+  W.ring = W.flags + std::max(Gmax_of(c), 1);
   W.H = dptr<double>(c, I.o_H);
   W.Escr = dptr<double>(c, I.o_Escr);
   W.y = dptr<double>(c, I.o_y);

@@ -91,7 +91,8 @@ struct KWork {
   double* X;                  // Lp: propagated vector
   double* F;                  // 24*n_elems element forces (slot-major)
   float* F32;
-  double* slots;              // 2 * G partial sums
+  unsigned long long* flags;  // G barrier generations
+  unsigned long long* ring;   // 8 * G all-reduce slots
   double* H;                  // (m_max+1) x m_max Hessenberg (row major, stride m_max)
   double* Escr;               // expm scratch 8 * m_max^2 (+ m_max^2 output staging)
   double* y;                  // m_max coefficients

@@ -350,56 +350,102 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // A team of G co-resident workgroups (cooperative launch) synchronised through device
-// memory; G == 1 degenerates to the workgroup barrier.  Waits are bounded: a timeout sets
-// the sticky error and marks the team dead so that every workgroup leaves the kernel.
+// memory; G == 1 degenerates to the workgroup barrier.
+//  * sync(): every workgroup publishes its barrier generation in its own flag (after a
+//    release fence) and polls all G flags (one thread per flag), then acquires.  Used where
+//    bulk data written by other workgroups is read next.
+//  * allreduce(): the workgroup partial itself is the signal: it is stored with an
+//    agent-coherent atomic into this round's slot of a ring (empty slots hold a sentinel
+//    NaN pattern) and every workgroup polls the G slots and sums them in rank order, so
+//    all workgroups obtain the same bits.  A workgroup empties its slot of round r-2 during
+//    round r, when every workgroup has provably finished reading it.  No cache flush.
+// Waits are bounded: a timeout sets the sticky error and marks the team dead so that every
+// workgroup leaves the kernel.
+constexpr unsigned long long kEmpty = 0x7ff4deadbeef1234ull;
+constexpr int kRing = 8;
+
+__device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct GridTeam {
   int G, rank;
-  unsigned long long* bar;
+  unsigned long long* flags;   // [G] barrier generations
+  unsigned long long* ring;    // [kRing * G] all-reduce slots
   int* err;
-  double* slots;
   unsigned long long gen;
-  int parity;
+  unsigned rnd;
   bool dead;
+
+  __device__ void timeout() {
+    atomicCAS(err, 0, kErrDevice);
+  }
 
   __device__ bool sync(int* lds_flag) {
     __syncthreads();
     if (G == 1) return true;
+    gen += 1;
     if (threadIdx.x == 0) {
-      gen += 1;
-      const unsigned long long target = gen * (unsigned long long)G;
+      *lds_flag = 1;
       __threadfence();
-      atomicAdd(bar, 1ull);
-      unsigned long long spins = 0;
-      int ok = 1;
-      while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(2);
-        if (++spins > (1ull << 26)) {
-          ok = 0;
-          atomicCAS(err, 0, kErrDevice);
-          break;
-        }
-      }
-      __threadfence();
-      *lds_flag = ok;
-    } else {
-      gen += 1;
+      st_agent(&flags[rank], gen);
     }
     __syncthreads();
-    const bool ok = *lds_flag != 0;
-    if (!ok) dead = true;
-    return ok;
+    bool ok = true;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) {
+      unsigned long long spins = 0;
+      while (ld_agent(&flags[i]) < gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ull << 26)) { ok = false; break; }
+      }
+    }
+    if (!ok) { *lds_flag = 0; timeout(); }
+    __syncthreads();
+    if (threadIdx.x == 0) __threadfence();
+    __syncthreads();
+    if (*lds_flag == 0) { dead = true; return false; }
+    return true;
   }
 
-  // all-reduce of one double per workgroup; fixed summation order on every workgroup
-  __device__ double allreduce(double partial, double* red, int* lds_flag) {
+  // all-reduce of one double per workgroup; fixed summation order on every workgroup.
+  // fenced = true also publishes this workgroup's earlier global stores and makes the other
+  // workgroups' ones visible (release before the partial, acquire after the slots): used
+  // where bulk data written before the reduction is gathered across slices afterwards.
+  __device__ double allreduce(double partial, double* red, int* lds_flag, bool fenced = false) {
+    if (threadIdx.x == 0) *lds_flag = 1;   // ordered before the polls by block_sum's barriers
     const double p = block_sum(partial, red);
     if (G == 1) return p;
-    if (threadIdx.x == 0) slots[parity * G + rank] = p;
-    if (!sync(lds_flag)) return 0.0;
+    unsigned long long* slot = ring + (size_t)(rnd % kRing) * G;
+    if (threadIdx.x == 0) {
+      if (fenced) __threadfence();
+      st_agent(&slot[rank], p == p ? (unsigned long long)__double_as_longlong(p) : 0x7ff8000000000000ull);
+    }
     double v = 0.0;
-    for (int i = threadIdx.x; i < G; i += blockDim.x) v += slots[parity * G + i];
-    parity ^= 1;
-    return block_sum(v, red);
+    bool ok = true;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) {
+      unsigned long long x, spins = 0;
+      while ((x = ld_agent(&slot[i])) == kEmpty) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1ull << 26)) { ok = false; break; }
+      }
+      v += __longlong_as_double((long long)x);
+    }
+    if (!ok) { *lds_flag = 0; timeout(); }
+    if (fenced) {             // acquire after every slot has been observed
+      __syncthreads();
+      if (threadIdx.x == 0) __threadfence();
+    }
+    const double tot = block_sum(v, red);
+    if (threadIdx.x == 0 && rnd >= 2) {
+      st_agent(&ring[(size_t)((rnd - 2) % kRing) * G + rank], kEmpty);
+      __builtin_amdgcn_s_waitcnt(0);   // the emptying store is performed before any later store
+    }
+    rnd += 1;
+    if (*lds_flag == 0) { dead = true; return 0.0; }
+    return tot;
   }
 };
 

@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
   double* red = lv + C;
   double* yb = red + 16;
   int* flag = (int*)(yb + kMaxM);
-  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, &A.W.ctrl->bar, &A.W.ctrl->err, A.W.slots, 0ull, 0, false};
+  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false};
   expv_body<T, MODEL>(tm, A, lw, lv, red, yb, flag);
 }
 
@@ -396,8 +396,14 @@ hipError_t expv_max_blocks(int prec, int model, int chunk, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds);
 }
 
+// empty all-reduce ring and zero barrier flags of a team before a launch
+__global__ void k_prep_team(unsigned long long* flags, unsigned long long* ring, int G) {
+  for (int i = threadIdx.x; i < G; i += blockDim.x) flags[i] = 0ull;
+  for (int i = threadIdx.x; i < kRing * G; i += blockDim.x) ring[i] = kEmpty;
+}
+
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
-  k_reset_ctrl<<<1, 1, 0, st>>>(a.W.ctrl, 0);
+  k_prep_team<<<1, 256, 0, st>>>(a.W.flags, a.W.ring, a.W.G);
   const void* fn = expv_kernel(prec, a.M.model);
   const size_t lds = expv_lds_bytes(a.W.chunk);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

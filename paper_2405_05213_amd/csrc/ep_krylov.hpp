@@ -26,7 +26,7 @@ struct BlockTeam {
     __syncthreads();
     return true;
   }
-  __device__ double allreduce(double p, double* red, int*) { return block_sum(p, red); }
+  __device__ double allreduce(double p, double* red, int*, bool = false) { return block_sum(p, red); }
 };
 
 struct ProjResult {
@@ -134,7 +134,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
           W.Wun[c0 + t] = w;
           part += w * w;
         }
-        hn = sqrt(tm.allreduce(part, red, flag));
+        hn = sqrt(tm.allreduce(part, red, flag, true));
         if (tm.dead) return R;
         if (lead && threadIdx.x == 0) W.H[(size_t)j * ldH + (j - 1)] = hn;
         hmax = fmax(hmax, hn);
@@ -183,7 +183,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
           W.X[c0 + i] = s;
           part += s * s;
         }
-        R.beta_next = sqrt(tm.allreduce(part, red, flag));
+        R.beta_next = sqrt(tm.allreduce(part, red, flag, true));
         R.converged = true;
         return R;
       }
@@ -221,7 +221,7 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
       W.X[c0 + i] = v;
       part += v * v;
     }
-    double beta = sqrt(tm.allreduce(part, red, flag));
+    double beta = sqrt(tm.allreduce(part, red, flag, true));
     if (tm.dead) return;
     bool ok = true;
     int hint_run = hint;
