@@ -218,6 +218,9 @@ ep_status ep_batch_get_state(ep_ctx* ctx, int32_t instance_id, double* t, double
 /* Per-instance statistics of the last step: corrector m and substeps. */
 ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs, int* last_m,
                              int* last_k, double* last_eps);
+/* Per-instance energies, as ep_get_energy. */
+ep_status ep_batch_get_energy(ep_ctx* ctx, int32_t instance_id, double* kinetic, double* strain,
+                              double* ext_work);
 
 #ifdef __cplusplus
 }

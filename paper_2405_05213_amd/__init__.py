@@ -3,4 +3,5 @@
 The numerical path lives in the HIP library libep.so (C ABI in include/ep.h); this package
 holds its build script and a thin ctypes binding.
 """
-from .ep import Context, EPError, EXPORTED, LIB_PATH, lib, solver_from_problem  # noqa: F401
+from .ep import (Batch, Context, EPError, EXPORTED, LIB_PATH, batch_from_problems, lib,  # noqa: F401
+                 solver_from_problem)

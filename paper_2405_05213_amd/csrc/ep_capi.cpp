@@ -53,7 +53,7 @@ struct Inst {
   // workspace offsets
   size_t o_xyz, o_conn, o_incp, o_inc, o_geo, o_geo32, o_vdet, o_mih, o_mh, o_p0, o_p0bar, o_faces, o_fincp,
       o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y,
-      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags;
+      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr;
   Mesh M{};
   KWork W{};
   // stepping state (host mirror)
@@ -82,6 +82,18 @@ struct ep_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t o_batch_tab = 0;
+  // batch
+  std::vector<BatchInst> btab;          // host mirror of the device records
+  std::vector<int> bids[3];             // instance ids per material model
+  size_t o_bids[3] = {0, 0, 0};
+  int max_lds_chunk = 0;
+  hipGraphExec_t bgraph = nullptr;
+  hipGraph_t bgraph_src = nullptr;
+  double bgraph_dt = 0.0;
+  ~ep_ctx() {
+    if (bgraph) (void)hipGraphExecDestroy(bgraph);
+    if (bgraph_src) (void)hipGraphDestroy(bgraph_src);
+  }
 };
 
 static ep_status fail(ep_ctx* c, ep_status s, const std::string& msg) {
@@ -223,6 +235,7 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_pv = L.take(8 * 2 * ((n3 + 255) / 256 + 1));
   I.o_eout = L.take(8 * 4);
   I.o_flags = L.take(4 * 4);
+  I.o_wscr = L.take(c->batch ? 8 * 2 * Lp : 8);
 }
 
 static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
@@ -234,7 +247,8 @@ static size_t plan_all(ep_ctx* c) {
     plan_inst(c, c->one, L, Gmax);
   } else {
     for (auto& I : c->insts) plan_inst(c, I, L, 1);
-    c->o_batch_tab = L.take(sizeof(ExpvArgs) * std::max<size_t>(c->insts.size(), 1) * 2);
+    c->o_batch_tab = L.take(sizeof(BatchInst) * std::max<size_t>(c->insts.size(), 1));
+    for (int k = 0; k < 3; ++k) c->o_bids[k] = L.take(4 * std::max<size_t>(c->insts.size(), 1));
   }
   return L.off + kAlign;
 }
@@ -276,7 +290,7 @@ static double auto_s0(const ep_ctx* c, const Inst& I) {
   return (load && nonzero_scale) ? 1.0 : 0.0;
 }
 
-static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk) {
+static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   hipStream_t st = c->stream;
   build_incidence(I);
   const size_t nf = I.faces.size() / 4;
@@ -343,7 +357,7 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk) {
   W.F = dptr<double>(c, I.o_F);
   W.F32 = dptr<float>(c, I.o_F32);
   W.flags = dptr<unsigned long long>(c, I.o_slots);
-  W.ring = W.flags + std::max(Gmax_of(c), 1);
+  W.ring = W.flags + std::max(Gslots, 1);
   W.H = dptr<double>(c, I.o_H);
   W.Escr = dptr<double>(c, I.o_Escr);
   W.y = dptr<double>(c, I.o_y);
@@ -351,6 +365,7 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk) {
   W.log = dptr<StepLog>(c, I.o_log);
   W.G = G;
   W.chunk = chunk;
+  W.wscr = dptr<double>(c, I.o_wscr);
   launch_reset_ctrl(W.ctrl, st);
   EP_HIP(c, hipGetLastError());
   EP_HIP(c, hipStreamSynchronize(st));
@@ -632,7 +647,7 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
       chunk = ((c->one.Lp + G - 1) / G + 63) / 64 * 64;
     }
     if (bpc < 1) return fail(c, EP_ERR_WORKSPACE, "Krylov vector slice does not fit in LDS");
-    s = setup_inst(c, c->one, G, chunk);
+    s = setup_inst(c, c->one, G, chunk, Gmax_of(c));
     if (s != EP_OK) return s;
   }
   c->bound = true;
@@ -896,6 +911,206 @@ ep_status ep_expv(ep_ctx* c, const double* u_lin, double tau, double pscale, con
   if (m_used) *m_used = h.ks[2].last_m;
   if (k_used) *k_used = h.ks[2].last_k;
   if (eps) *eps = h.ks[2].last_eps;
+  return EP_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================== batches
+extern "C" {
+
+ep_status ep_batch_add_instance(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
+                                ep_model model, const double* params, int n_params, double rho, int64_t n_dirichlet,
+                                const int32_t* dofs, int64_t n_faces, const int32_t* faces, const double t0[3],
+                                int64_t n_knots, const double* kt, const double* ks, int32_t* id) {
+  if (!c || !id) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "ep_batch_add_instance after ep_bind_workspace");
+  if (c->mesh_set) return fail(c, EP_ERR_ORDER, "single-instance context: cannot add batch instances");
+  ep_status s = check_mesh(c, n_nodes, xyz, n_elems, conn);
+  if (s != EP_OK) return s;
+  s = check_material(c, (int)model, params, n_params, rho);
+  if (s != EP_OK) return s;
+  if (n_dirichlet < 0 || (n_dirichlet > 0 && !dofs)) return fail(c, EP_ERR_ARG, "bad Dirichlet list");
+  for (int64_t i = 0; i < n_dirichlet; ++i)
+    if (dofs[i] < 0 || dofs[i] >= 3 * n_nodes) return fail(c, EP_ERR_ARG, "Dirichlet DOF out of range");
+  s = check_traction(c, n_nodes, n_faces, faces, t0, n_knots, kt, ks);
+  if (s != EP_OK) return s;
+  Inst I;
+  fill_mesh(I, n_nodes, xyz, n_elems, conn);
+  I.model = (int)model;
+  for (int i = 0; i < 4; ++i) I.mp[i] = i < n_params ? params[i] : 0.0;
+  I.rho = rho;
+  I.clamped.assign(dofs, dofs + n_dirichlet);
+  fill_traction(I, n_faces, faces, t0, n_knots, kt, ks);
+  c->batch = true;
+  c->insts.push_back(std::move(I));
+  *id = (int32_t)(c->insts.size() - 1);
+  return EP_OK;
+}
+
+ep_status ep_batch_bind(ep_ctx* c) {
+  const int n = (int)c->insts.size();
+  c->btab.assign(n, BatchInst{});
+  c->max_lds_chunk = 0;
+  for (int k = 0; k < 3; ++k) c->bids[k].clear();
+  for (int i = 0; i < n; ++i) {
+    Inst& I = c->insts[i];
+    ep_status s = setup_inst(c, I, 1, I.Lp, 1);
+    if (s != EP_OK) return fail(c, s, "batch instance " + std::to_string(i) + ": " + c->err);
+    BatchInst& B = c->btab[i];
+    B.M = I.M;
+    B.W = I.W;
+    B.S = dptr<double>(c, I.o_S);
+    B.hist = dptr<double>(c, I.o_hist);
+    B.t = 0.0;
+    B.step_idx = 0;
+    B.nhist = 0;
+    B.hist_new = B.hist_old = -1;
+    B.use_lds = I.Lp <= kMaxChunk ? 1 : 0;
+    if (B.use_lds) c->max_lds_chunk = std::max(c->max_lds_chunk, I.Lp);
+    c->bids[I.model].push_back(i);
+  }
+  EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_batch_tab), c->btab.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice));
+  for (int k = 0; k < 3; ++k)
+    if (!c->bids[k].empty())
+      EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_bids[k]), c->bids[k].data(), 4 * c->bids[k].size(),
+                          hipMemcpyHostToDevice));
+  return EP_OK;
+}
+
+static ep_status need_batch(ep_ctx* c, int32_t id) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound || !c->batch) return fail(c, EP_ERR_ORDER, "needs a bound batch context");
+  if (id < 0 || id >= (int32_t)c->insts.size()) return fail(c, EP_ERR_ARG, "instance id out of range");
+  return EP_OK;
+}
+
+static ep_status pull_record(ep_ctx* c, int32_t id) {
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  EP_HIP(c, hipMemcpy(&c->btab[id], dptr<BatchInst>(c, c->o_batch_tab) + id, sizeof(BatchInst),
+                      hipMemcpyDeviceToHost));
+  return EP_OK;
+}
+
+ep_status ep_batch_set_state(ep_ctx* c, int32_t id, double t, const double* u, const double* v) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  if (!u || !v || !std::isfinite(t)) return fail(c, EP_ERR_ARG, "bad state arguments");
+  Inst& I = c->insts[id];
+  for (int i = 0; i < I.n3; ++i)
+    if (!std::isfinite(u[i]) || !std::isfinite(v[i])) return fail(c, EP_ERR_ARG, "non-finite state");
+  s = pull_record(c, id);
+  if (s != EP_OK) return s;
+  double* st = dptr<double>(c, I.o_stage);
+  EP_HIP(c, hipMemcpyAsync(st, u, 8 * (size_t)I.n3, hipMemcpyHostToDevice, c->stream));
+  EP_HIP(c, hipMemcpyAsync(st + I.n3, v, 8 * (size_t)I.n3, hipMemcpyHostToDevice, c->stream));
+  launch_set_state(I.n3, I.Lp, I.M.mh, st, st + I.n3, I.M.s0, dptr<double>(c, I.o_S), c->stream);
+  launch_reset_ctrl(I.W.ctrl, c->stream);
+  EP_HIP(c, hipGetLastError());
+  BatchInst& B = c->btab[id];
+  B.t = t;
+  B.step_idx = 0;
+  B.nhist = 0;
+  B.hist_new = B.hist_old = -1;
+  EP_HIP(c, hipMemcpyAsync(dptr<BatchInst>(c, c->o_batch_tab) + id, &B, sizeof(BatchInst), hipMemcpyHostToDevice,
+                           c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  I.state_set = true;
+  return EP_OK;
+}
+
+static ep_status batch_launch_all(ep_ctx* c, double dt, int n_steps, hipStream_t st) {
+  for (int k = 0; k < 3; ++k) {
+    if (c->bids[k].empty()) continue;
+    EP_HIP(c, launch_batch(dptr<BatchInst>(c, c->o_batch_tab), dptr<int>(c, c->o_bids[k]), (int)c->bids[k].size(),
+                           k, c->cfg, dt, n_steps, c->max_lds_chunk, st));
+  }
+  return EP_OK;
+}
+
+ep_status ep_batch_step(ep_ctx* c, double dt, int64_t n) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound || !c->batch) return fail(c, EP_ERR_ORDER, "needs a bound batch context");
+  if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return fail(c, EP_ERR_ARG, "need dt > 0 and n_steps >= 0");
+  for (auto& I : c->insts)
+    if (!I.state_set) return fail(c, EP_ERR_ORDER, "every instance needs ep_batch_set_state");
+  if (n == 0) return EP_OK;
+  // one step = one launch per material model present, captured once into a graph and replayed
+  if (c->bgraph == nullptr || c->bgraph_dt != dt) {
+    if (c->bgraph) { (void)hipGraphExecDestroy(c->bgraph); c->bgraph = nullptr; }
+    if (c->bgraph_src) { (void)hipGraphDestroy(c->bgraph_src); c->bgraph_src = nullptr; }
+    hipStream_t cs;
+    EP_HIP(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    ep_status s = EP_OK;
+    if (e == hipSuccess) s = batch_launch_all(c, dt, 1, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || e2 != hipSuccess || s != EP_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      if (s != EP_OK) return s;
+      return fail(c, EP_ERR_HIP, "graph capture of the batch step failed");
+    }
+    c->bgraph_src = g;
+    EP_HIP(c, hipGraphInstantiate(&c->bgraph, g, nullptr, nullptr, 0));
+    c->bgraph_dt = dt;
+  }
+  for (int64_t i = 0; i < n; ++i) EP_HIP(c, hipGraphLaunch(c->bgraph, c->stream));
+  return EP_OK;
+}
+
+ep_status ep_batch_get_state(ep_ctx* c, int32_t id, double* t, double* u, double* v) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  if (!t || !u || !v) return fail(c, EP_ERR_ARG, "null output");
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  s = pull_record(c, id);
+  if (s != EP_OK) return s;
+  Inst& I = c->insts[id];
+  double* st = dptr<double>(c, I.o_stage);
+  launch_get_state(I.n3, I.M.mih, dptr<double>(c, I.o_S), st, st + I.n3, c->stream);
+  EP_HIP(c, hipGetLastError());
+  EP_HIP(c, hipMemcpyAsync(u, st, 8 * (size_t)I.n3, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipMemcpyAsync(v, st + I.n3, 8 * (size_t)I.n3, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  *t = c->btab[id].t;
+  return EP_OK;
+}
+
+ep_status ep_batch_get_stats(ep_ctx* c, int32_t id, int64_t* matvecs, int* last_m, int* last_k, double* last_eps) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  Ctrl h;
+  EP_HIP(c, hipMemcpy(&h, c->insts[id].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  if (matvecs) *matvecs = h.ks[0].matvecs + h.ks[1].matvecs;
+  if (last_m) *last_m = h.ks[0].last_m;
+  if (last_k) *last_k = h.ks[0].last_k;
+  if (last_eps) *last_eps = h.ks[0].last_eps;
+  return EP_OK;
+}
+
+ep_status ep_batch_get_energy(ep_ctx* c, int32_t id, double* ke, double* se, double* we) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  if (!ke || !se || !we) return fail(c, EP_ERR_ARG, "null output");
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  s = pull_record(c, id);
+  if (s != EP_OK) return s;
+  Inst& I = c->insts[id];
+  double* out = dptr<double>(c, I.o_eout);
+  launch_energy(I.M, dptr<double>(c, I.o_S), c->btab[id].t, dptr<double>(c, I.o_pe), dptr<double>(c, I.o_pv), out,
+                c->stream);
+  EP_HIP(c, hipGetLastError());
+  double h[3];
+  EP_HIP(c, hipMemcpyAsync(h, out, 24, hipMemcpyDeviceToHost, c->stream));
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  *ke = h[0];
+  *se = h[1];
+  *we = h[2];
   return EP_OK;
 }
 

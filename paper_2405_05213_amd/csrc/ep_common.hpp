@@ -100,6 +100,20 @@ struct KWork {
   StepLog* log;
   int G;                      // workgroups of the team
   int chunk;                  // Krylov-vector entries owned by each workgroup
+  double* wscr;               // 2 * Lp: slice buffers in device memory when they exceed LDS
+};
+
+// Device-side record of one instance of a batch: the stepping state lives on the device so
+// that one step is a fixed launch (replayable from a captured graph).
+struct BatchInst {
+  Mesh M;
+  KWork W;
+  double* S;                  // wbar (Lp)
+  double* hist;               // 3 * n3 midpoint displacements
+  double t;
+  long long step_idx;
+  int nhist, hist_new, hist_old;
+  int use_lds;                // slice buffers in LDS (1) or in W.wscr (0)
 };
 
 // One launch of the persistent projection kernel: wbar_out = exp(tau A) wbar_in.

@@ -29,4 +29,8 @@ int energy_blocks(const Mesh& M);
 int energy_vec_blocks(const Mesh& M);
 void launch_energy(const Mesh& M, const double* S, double t, double* pe, double* pv, double* out, hipStream_t st);
 
+size_t batch_lds_bytes(int max_lds_chunk);
+hipError_t launch_batch(BatchInst* tab, const int* ids, int count, int model, const KrylovCfg& cfg, double dt,
+                        int n_steps, int max_lds_chunk, hipStream_t st);
+
 }  // namespace ep

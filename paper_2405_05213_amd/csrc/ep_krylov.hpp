@@ -286,6 +286,8 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
       }
     }
   }
+  // outputs and the adaptive state are visible to the whole team before anything reads them
+  tm.sync(flag);
 }
 
 }  // namespace ep

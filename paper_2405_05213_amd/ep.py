@@ -65,6 +65,7 @@ _SIGS = {
     "ep_batch_step": [_vp, _dbl, _i64],
     "ep_batch_get_state": [_vp, _i32, _P(_dbl), _vp, _vp],
     "ep_batch_get_stats": [_vp, _i32, _P(_i64), _P(C.c_int), _P(C.c_int), _P(_dbl)],
+    "ep_batch_get_energy": [_vp, _i32, _P(_dbl), _P(_dbl), _P(_dbl)],
 }
 EXPORTED = sorted(_SIGS)
 
@@ -238,6 +239,66 @@ class Context:
         self._call("ep_expv", _ptr(u_lin), float(tau), float(pscale), _ptr(w), _ptr(y), C.byref(m), C.byref(k),
                    C.byref(e))
         return m.value, k.value, e.value
+
+
+class Batch(Context):
+    """A batch context: many independent instances advanced together (one launch per step)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        super().__init__(device, stream)
+        self.n_nodes_of = []
+
+    def add(self, prob) -> int:
+        xyz, conn = _f64(prob.xyz), _i32a(prob.conn)
+        p = _f64(prob.params)
+        cl = _i32a(prob.clamped)
+        f = _i32a(prob.faces).reshape(-1, 4)
+        t0 = _f64(prob.t0)
+        kt, ks = _f64(prob.knots_t), _f64(prob.knots_s)
+        iid = C.c_int32()
+        self._call("ep_batch_add_instance", xyz.shape[0], _ptr(xyz), conn.shape[0], _ptr(conn), MODELS[prob.model],
+                   _ptr(p), p.size, float(prob.rho), cl.size, _ptr(cl), f.shape[0], _ptr(f), _ptr(t0), kt.size,
+                   _ptr(kt), _ptr(ks), C.byref(iid))
+        self.n_nodes_of.append(xyz.shape[0])
+        return iid.value
+
+    def set_state(self, iid, t, u, v):
+        u, v = _f64(u), _f64(v)
+        self._call("ep_batch_set_state", int(iid), float(t), _ptr(u), _ptr(v))
+
+    def step(self, dt, n_steps=1):
+        self._call("ep_batch_step", float(dt), int(n_steps))
+
+    def get_state(self, iid):
+        t = C.c_double()
+        n = 3 * self.n_nodes_of[iid]
+        u, v = np.empty(n), np.empty(n)
+        self._call("ep_batch_get_state", int(iid), C.byref(t), _ptr(u), _ptr(v))
+        return t.value, u, v
+
+    def stats(self, iid):
+        mv, m, k, e = C.c_int64(), C.c_int(), C.c_int(), C.c_double()
+        self._call("ep_batch_get_stats", int(iid), C.byref(mv), C.byref(m), C.byref(k), C.byref(e))
+        return {"matvecs": mv.value, "m": m.value, "k": k.value, "eps": e.value}
+
+    def energy(self, iid):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        self._call("ep_batch_get_energy", int(iid), C.byref(a), C.byref(b), C.byref(c))
+        return a.value, b.value, c.value
+
+
+def batch_from_problems(probs, device=0, tol=None, m_max=32, check_every=4, m_fixed=0, k_fixed=0,
+                        max_substeps=64, s0=-1.0, precision="f64", stream=None):
+    """Batch context with one instance per workloads.Problem, bound and at the initial states."""
+    b = Batch(device, stream=stream)
+    for p in probs:
+        b.add(p)
+    b.set_krylov(probs[0].tol if tol is None else tol, m_max, check_every, m_fixed, k_fixed, max_substeps, s0)
+    b.set_precision(precision)
+    b.bind()
+    for i, p in enumerate(probs):
+        b.set_state(i, 0.0, p.u0, p.v0)
+    return b
 
 
 def solver_from_problem(prob, device=0, tol=None, m_max=64, check_every=4, m_fixed=0, k_fixed=0,
