@@ -293,6 +293,143 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
   return ok;
 }
 
+// ---------------------------------------------------------------------------------------
+// Element force with one lane per Gauss point: 8 consecutive lanes share element e (all 8
+// must call with the same e).  Each lane builds grad x (and grad u of the secant sets) at
+// its point from the gathered nodal values, forms its stress and its contribution to the 24
+// nodal forces; a 3-round reduce-scatter over the 8 lanes (12 + 6 + 3 exchanges) leaves
+// lane q with the summed force of node q, which it stores to its element slot.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T shfl_x(T v, int o) { return __shfl_xor(v, o, 64); }
+
+// Lanes per element of the operator's element kernel: the FP64 secant materials keep too
+// many values live for one lane per element (register spills), so they spread an element
+// over 8 lanes; the linear and FP32 kernels fit one lane per element and avoid the 8-fold
+// gathers.
+template <typename T, int MODEL>
+__host__ __device__ constexpr int elem_lanes() { return (sizeof(T) == 8 && MODEL != kLinear) ? 8 : 1; }
+
+template <typename T>
+__device__ __forceinline__ void grad_gather(const QFactors<T>& Q, const int (&nd)[8], const double* v, double sc,
+                                            const double* mih, const T* Jinv, T (&G)[3][3]) {
+  T Dxi[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Dxi[i][j] = T(0);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T d0 = Q.dN(a, 0), d1 = Q.dN(a, 1), d2 = Q.dN(a, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t d = (size_t)nd[a] * 3 + i;
+      double xv = v[d] * sc;
+      if (mih) xv *= mih[d];
+      const T x = T(xv);
+      Dxi[i][0] += x * d0;
+      Dxi[i][1] += x * d1;
+      Dxi[i][2] += x * d2;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      G[i][k] = Dxi[i][0] * Jinv[0 * 3 + k] + Dxi[i][1] * Jinv[1 * 3 + k] + Dxi[i][2] * Jinv[2 * 3 + k];
+}
+
+template <typename T, int MODEL>
+__device__ __forceinline__ bool elem_force_qp(const Mesh& M, const OpArgs& op, int e, const double* src,
+                                              double srcscale, bool scale_mih, T* F) {
+  const int q = threadIdx.x & 7;
+  const QFactors<T> Q(q);
+  int nd[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+  T Jinv[9], wdet;
+  const size_t gi = (M.congruent ? (size_t)q : (size_t)e * 8 + q) * 10;
+  if (sizeof(T) == 8) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo[gi + k]);
+    wdet = T(M.geo[gi + 9]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo32[gi + k]);
+    wdet = T(M.geo32[gi + 9]);
+  }
+  T X[3][3];
+  grad_gather(Q, nd, src, srcscale, scale_mih ? M.mih : nullptr, Jinv, X);
+  T S[3][3];
+  bool ok = true;
+  const int nsets = (MODEL == kLinear) ? 0 : op.nsets;
+  if (nsets == 0) {
+    double lam_d, mu_d;
+    rest_lame(M.model, M.mp, lam_d, mu_d);
+    const T lam = T(lam_d), mu = T(mu_d);
+    const T tr = X[0][0] + X[1][1] + X[2][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) S[i][k] = mu * (X[i][k] + X[k][i]) + (i == k ? lam * tr : T(0));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) S[i][k] = T(0);
+    if (MODEL != kLinear) {
+      for (int s = 0; s < nsets; ++s) {
+        T Du[3][3];
+        Secant<T> sc;
+        grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
+        ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
+        secant_apply(sc, T(op.wts[s]), X, S);
+      }
+    }
+  }
+  // contribution of this point: f_a,i = sum_j St[i][j] dN_a/dxi_j, St = wdet S Jinv^T
+  T St[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      St[i][j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
+  T f[8][3];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T d0 = Q.dN(a, 0), d1 = Q.dN(a, 1), d2 = Q.dN(a, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[a][i] = St[i][0] * d0 + St[i][1] * d1 + St[i][2] * d2;
+  }
+  // reduce-scatter over the 8 lanes: keep the half of the nodes that matches the lane bit
+  const bool b4 = (q >> 2) & 1, b2 = (q >> 1) & 1, b1 = q & 1;
+  T k4[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T send = b4 ? f[a][i] : f[a + 4][i];
+      const T keep = b4 ? f[a + 4][i] : f[a][i];
+      k4[a][i] = keep + shfl_x(send, 4);
+    }
+  T k2[2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T send = b2 ? k4[a][i] : k4[a + 2][i];
+      const T keep = b2 ? k4[a + 2][i] : k4[a][i];
+      k2[a][i] = keep + shfl_x(send, 2);
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T send = b1 ? k2[0][i] : k2[1][i];
+    const T keep = b1 ? k2[1][i] : k2[0][i];
+    F[((size_t)q * M.n_elems + e) * 3 + i] = keep + shfl_x(send, 1);
+  }
+  return ok;
+}
+
 template <typename T>
 __device__ __forceinline__ void store_force(const Mesh& M, int e, const T (&f)[8][3], T* F) {
 #pragma unroll

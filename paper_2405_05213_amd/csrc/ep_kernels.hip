@@ -204,11 +204,17 @@ template <typename T, int MODEL>
 __global__ __launch_bounds__(256) void k_elem_forces(Mesh M, OpArgs op, const double* __restrict__ src,
                                                      double srcscale, int scale_mih, T* __restrict__ F,
                                                      int* __restrict__ err) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int lanes = elem_lanes<T, MODEL>();
+  const int e = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) / lanes);
   if (e >= M.n_elems) return;
-  T f[8][3];
-  const bool ok = elem_force<T, MODEL>(M, op, e, src, srcscale, scale_mih != 0, f);
-  store_force(M, e, f, F);
+  bool ok;
+  if (lanes == 8) {
+    ok = elem_force_qp<T, MODEL>(M, op, e, src, srcscale, scale_mih != 0, F);
+  } else {
+    T f[8][3];
+    ok = elem_force<T, MODEL>(M, op, e, src, srcscale, scale_mih != 0, f);
+    store_force(M, e, f, F);
+  }
   if (!ok) atomicCAS(err, 0, kErrInverted);
 }
 
@@ -446,7 +452,7 @@ void launch_reset_ctrl(Ctrl* c, hipStream_t st) { k_reset_ctrl<<<1, 1, 0, st>>>(
 template <typename T>
 static void elem_forces_t(const Mesh& M, const OpArgs& op, const double* src, double sc, int scale_mih, T* F, int* err,
                           hipStream_t st) {
-  const int nb = nblk(M.n_elems, 256);
+  const int nb = nblk((long long)M.n_elems * 8, 256);
   if (M.n_elems == 0) return;
   if (M.model == kLinear) k_elem_forces<T, kLinear><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
   else if (M.model == kNH) k_elem_forces<T, kNH><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);

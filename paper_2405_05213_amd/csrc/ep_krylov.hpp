@@ -71,10 +71,16 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
   for (int j = 1; j <= mcap; ++j) {
     // ---- operator apply, part 1: element forces of the u-part of v_{j-1}
     bool okA = true;
-    for (int e = tm.rank * blockDim.x + threadIdx.x; e < M.n_elems; e += tm.G * blockDim.x) {
-      T fe[8][3];
-      okA &= elem_force<T, MODEL>(M, A.op, e, src, hinv, true, fe);
-      store_force(M, e, fe, F);
+    if (elem_lanes<T, MODEL>() == 8) {
+      // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
+      for (int e = (tm.rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (tm.G * blockDim.x) >> 3)
+        okA &= elem_force_qp<T, MODEL>(M, A.op, e, src, hinv, true, F);
+    } else {
+      for (int e = tm.rank * blockDim.x + threadIdx.x; e < M.n_elems; e += tm.G * blockDim.x) {
+        T fe[8][3];
+        okA &= elem_force<T, MODEL>(M, A.op, e, src, hinv, true, fe);
+        store_force(M, e, fe, F);
+      }
     }
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;

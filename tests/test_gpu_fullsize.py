@@ -1,0 +1,67 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark uses
+(needs an MI355X).  Where a whole oracle step would take minutes (the 64^3 block), the
+operator and the energies are compared at full size instead."""
+import numpy as np
+import pytest
+
+from workloads import config
+from oracle.stepper import Propagator
+from tests.gpu_util import pair, rel, say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+def test_c2_full_step():
+    """80x8x8 linear cantilever, dt = 1e-4, the benchmark's calibrated mode (m = 48, 4 substeps)."""
+    say("[full] c2 one step m=48 k=4")
+    p = config("c2")
+    ctx, orc = pair(p, m_max=64, m_fixed=48, k_fixed=4)
+    ctx.step(p.dt, 1)
+    t, u, v = ctx.get_state()
+    orc.step(p.dt)
+    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
+
+
+def test_c3_full_step():
+    """160x16x16 compressible Neo-Hookean cantilever, first predictor-corrector step."""
+    say("[full] c3 one step")
+    p = config("c3")
+    ctx, orc = pair(p, m_max=64)
+    ctx.step(p.dt, 1)
+    t, u, v = ctx.get_state()
+    orc.step(p.dt)
+    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
+    assert ctx.step_log(1)["m_corr"][0] == orc.log[0]["corr"]["m"][0]
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("mixed_f32", 3e-6)])
+def test_c4_full_operator_and_energy(prec, tol):
+    """64^3 decoupled Neo-Hookean (Yeoh) block: H(u) x at a deformed state, full size."""
+    say(f"[full] c4 operator {prec}")
+    p = config("c4")
+    ctx, orc = pair(p, m_max=16, precision=prec)
+    rng = np.random.default_rng(21)
+    n3 = 3 * p.n_nodes
+    u = np.zeros(n3)
+    u[orc.free] = 2e-3 * rng.normal(size=orc.N)
+    x = np.zeros(n3)
+    x[orc.free] = rng.normal(size=orc.N)
+    y = torch.zeros(n3, dtype=torch.float64, device=DEV)
+    ctx.apply_H(_t(u), _t(x), y)
+    ref = orc.fem.H_apply(u, x)
+    assert rel(y.cpu().numpy()[orc.free], ref[orc.free]) < tol
+    # energies of a deformed, moving state
+    v = np.zeros(n3)
+    v[orc.free] = 1e-3 * rng.normal(size=orc.N)
+    ctx.set_state(0.05, u, v)
+    ke, se, we = ctx.energy()
+    o = Propagator(p.with_(u0=u, v0=v))
+    o.t = 0.05
+    ko, so, wo = o.energies()
+    assert abs(ke - ko) <= 1e-12 * ko and abs(se - so) <= 1e-11 * so and abs(we - wo) <= 1e-12 * abs(wo)
