@@ -45,7 +45,19 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run 3 device copies of 256 MiB (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
+
+
+def copy_probe(torch):
+    """A plain device-to-device copy of known size: 256 MiB read + 256 MiB written per dispatch."""
+    a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
 
 
 def log(args, *a):
@@ -101,12 +113,17 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
     lg = cal.step_log(nwarm)
     m_cal, k_cal = int(lg["m_corr"][-1]), int(lg["k_corr"][-1])
     m_pred = int(lg["m_pred"][-1])
+    tuned_G = workgroups
+    if workgroups == 0:
+        # the project's autotuner picks the team size of the persistent kernel
+        tuned_G, tuned_ms = cal.autotune(prob.dt, m_trial=max(8, min(m_cal, 48)), trials=2)
+        log(args, f"  {prob.name} {precision}: autotuned workgroups = {tuned_G} ({tuned_ms:.3f} ms/projection)")
     if adaptive:
         ctx = cal
     else:
         del cal
         ctx = solver_from_problem(prob, m_max=m_max, m_fixed=max(m_cal, m_pred), k_fixed=k_cal,
-                                  precision=precision, workgroups=workgroups, stream=stream.cuda_stream)
+                                  precision=precision, workgroups=tuned_G, stream=stream.cuda_stream)
         ctx.step(prob.dt, nwarm)
     ctx.sync()
     e_ref = ctx.energy() if prob.model == "linear" else (0.0, 0.0, 0.0)
@@ -126,7 +143,7 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
         "ms_per_step": float(np.mean(ms)), "time_steps_per_s": steps / gpu_s,
         "dof_matvecs_per_s": prob.n_free * mv / gpu_s, "m": st1["m"], "k": st1["k"],
         "m_fixed": max(m_cal, m_pred), "energy_rel_err": energy_err(e_ref, e1) if prob.model == "linear" else None,
-        "matvecs": mv, "wall_s": wall, "step_ms": ms, "ctx": ctx,
+        "matvecs": mv, "wall_s": wall, "step_ms": ms, "ctx": ctx, "workgroups": tuned_G,
     }
 
 
@@ -169,6 +186,8 @@ def main():
         sys.exit(1)
     stream = torch.cuda.current_stream()
     prob = config(args.config, dt=args.dt)
+    if args.copy_probe:
+        copy_probe(torch)
 
     head = run_single(prob, args.precision, args.steps, args.warmup, args.m_max, args.workgroups,
                       args.adaptive, stream, torch, args)
@@ -194,7 +213,7 @@ def main():
                         f"{prob.n_free} free DOFs, dt={prob.dt:g} s, tol={prob.tol:g}",
             "dt": prob.dt, "m": m_used, "substeps": k_used,
             "m_mode": "adaptive" if args.adaptive else "calibrated then fixed",
-            "precision": args.precision, "free_dofs": prob.n_free,
+            "precision": args.precision, "free_dofs": prob.n_free, "workgroups": head["workgroups"],
         },
         "time_steps_per_s": head["time_steps_per_s"],
         "energy_rel_err": head["energy_rel_err"],
@@ -220,7 +239,7 @@ def main():
                 extra[f"{name}_{prec}"] = {k: v for k, v in r.items() if k not in ("ctx", "step_ms", "energy_rel_err")}
                 extra[f"{name}_{prec}"]["free_dofs"] = p.n_free
                 del r
-        probs = batch_instances(256, seed=5, dt=1e-4)
+        probs = batch_instances(256, seed=5, dt=2.5e-5)
         for prec in ("f64", "mixed_f32"):
             extra[f"c5_batch_{prec}"] = run_batch(probs, prec, 30, 32, stream, torch, args)
         result["extra"] = extra

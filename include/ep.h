@@ -118,8 +118,16 @@ ep_status ep_set_krylov(ep_ctx* ctx, double tol, int m_max, int check_every, int
 
 ep_status ep_set_precision(ep_ctx* ctx, ep_precision prec);
 
-/* Number of workgroups of the persistent Krylov kernel (0 = automatic / autotuned). */
+/* Number of workgroups of the persistent Krylov kernel (0 = automatic). */
 ep_status ep_set_launch(ep_ctx* ctx, int workgroups);
+
+/* Autotuner of the persistent Krylov kernel's launch: after ep_set_state, times `trials`
+ * fixed-size projections (m_trial Arnoldi steps of dt * A at the current state) for every
+ * feasible workgroup count (LDS slice and co-residency limits) and keeps the fastest for
+ * this context.  Reports the choice and its time per projection (ms).  Uses only scratch
+ * memory; the state is unchanged. */
+ep_status ep_autotune(ep_ctx* ctx, double dt, int m_trial, int trials, int* best_workgroups,
+                      double* best_ms);
 
 /* ------------------------------------------------------------------ workspace
  * All device memory is caller-owned: query the size, allocate (e.g. a torch uint8

@@ -100,15 +100,17 @@ __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double
   return true;
 }
 
-constexpr int kBatchHead = 16 + kMaxM + 16;   // doubles of LDS before the slice buffers
+constexpr int kBatchHead = 32 + kMaxM + 16;   // doubles of LDS before the slice buffers
 
 template <typename T, int MODEL>
 __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* ids, KrylovCfg cfg, double dt,
                                                     int n_steps) {
   extern __shared__ double lds[];
   double* red = lds;
-  double* yb = lds + 16;
-  int* flag = (int*)(lds + 16 + kMaxM);
+  double* yb = lds + 32;
+  int* flag = (int*)(lds + 32 + kMaxM);
+  if (threadIdx.x == 0) *flag = 1;
+  __syncthreads();
   const int id = ids[blockIdx.x];
   BatchInst B = tab[id];
   double* lw;

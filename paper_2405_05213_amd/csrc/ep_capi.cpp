@@ -20,7 +20,7 @@ using namespace ep;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr long long kMaxChunk = 9984;     // (2 * 9984 + 272) doubles of LDS fit in 160 KB
+constexpr long long kMaxChunk = 9984;     // (2 * 9984 + 304) doubles of LDS fit in 160 KB
 
 struct Layout {
   size_t off = 0;
@@ -911,6 +911,80 @@ ep_status ep_expv(ep_ctx* c, const double* u_lin, double tau, double pscale, con
   if (m_used) *m_used = h.ks[2].last_m;
   if (k_used) *k_used = h.ks[2].last_k;
   if (eps) *eps = h.ks[2].last_eps;
+  return EP_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================== autotuner
+extern "C" {
+
+ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G, double* best_ms) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  if (!I.state_set) return fail(c, EP_ERR_ORDER, "call ep_set_state first");
+  if (!(dt > 0.0) || !std::isfinite(dt) || m_trial < 1 || trials < 1 || trials > 1000)
+    return fail(c, EP_ERR_ARG, "need dt > 0, m_trial >= 1, 1 <= trials <= 1000");
+  const int m = std::min(m_trial, c->cfg.m_max);
+  // linearisation point of the nonlinear operator: the current displacement (staging area)
+  double* ucur = dptr<double>(c, I.o_stage);
+  launch_get_state(I.n3, I.M.mih, dptr<double>(c, I.o_S), ucur, nullptr, c->stream);
+  EP_HIP(c, hipGetLastError());
+  ExpvArgs a{};
+  a.M = I.M;
+  a.W = I.W;
+  a.cfg = c->cfg;
+  a.cfg.m_fixed = m;
+  a.cfg.k_fixed = 1;
+  a.op.tau = dt;
+  a.op.t_eval = I.t + 0.5 * dt;
+  a.op.nsets = I.model == EP_LINEAR ? 0 : 1;
+  a.op.ulin[0] = ucur;
+  a.op.wts[0] = 1.0;
+  a.kind = 2;
+  a.x_in = dptr<double>(c, I.o_S);
+  a.x_out = I.W.X;
+  a.out_mode = 2;
+  a.log_idx = -1;
+  static const int cand[] = {1, 2, 4, 8, 12, 16, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512};
+  hipEvent_t e0, e1;
+  EP_HIP(c, hipEventCreate(&e0));
+  EP_HIP(c, hipEventCreate(&e1));
+  int bestG = I.W.G, bestC = I.W.chunk;
+  float best = 1e30f;
+  const int Gslots = Gmax_of(c);
+  for (int G : cand) {
+    if (G > Gslots || G > std::max(1, I.Lp / 64)) continue;
+    int chunk = ((I.Lp + G - 1) / G + 63) / 64 * 64;
+    if (chunk > kMaxChunk) continue;
+    int bpc = 0;
+    if (expv_max_blocks(c->cfg.prec, I.model, chunk, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
+    a.W.G = G;
+    a.W.chunk = chunk;
+    if (launch_expv(a, c->cfg.prec, c->stream) != hipSuccess) continue;   // warm-up
+    (void)hipEventRecord(e0, c->stream);
+    bool ok = true;
+    for (int r = 0; r < trials && ok; ++r) ok = launch_expv(a, c->cfg.prec, c->stream) == hipSuccess;
+    (void)hipEventRecord(e1, c->stream);
+    if (hipEventSynchronize(e1) != hipSuccess || !ok) continue;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= trials;
+    if (ms < best) {
+      best = ms;
+      bestG = G;
+      bestC = chunk;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s = read_err(c, I);
+  if (s != EP_OK) return s;
+  I.W.G = bestG;
+  I.W.chunk = bestC;
+  if (best_G) *best_G = bestG;
+  if (best_ms) *best_ms = best < 1e29f ? best : -1.0;
   return EP_OK;
 }
 

@@ -489,23 +489,43 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // A team of G co-resident workgroups (cooperative launch) synchronised through device
 // memory; G == 1 degenerates to the workgroup barrier.
 //  * sync(): every workgroup publishes its barrier generation in its own flag (after a
-//    release fence) and polls all G flags (one thread per flag), then acquires.  Used where
-//    bulk data written by other workgroups is read next.
-//  * allreduce(): the workgroup partial itself is the signal: it is stored with an
-//    agent-coherent atomic into this round's slot of a ring (empty slots hold a sentinel
-//    NaN pattern) and every workgroup polls the G slots and sums them in rank order, so
-//    all workgroups obtain the same bits.  A workgroup empties its slot of round r-2 during
-//    round r, when every workgroup has provably finished reading it.  No cache flush.
-// Waits are bounded: a timeout sets the sticky error and marks the team dead so that every
-// workgroup leaves the kernel.
+//    release fence) and polls all G flags, then acquires.  Used where bulk data written by
+//    other workgroups is read next.
+//  * post() / wait(): an all-reduce split in two so that independent loads can be issued
+//    while it is in flight.  The workgroup partial itself is the signal: post() stores it
+//    with an agent-coherent atomic into this round's slot of a ring (empty slots hold a
+//    sentinel NaN pattern); wait() has every wave poll the G slots and sum them in rank
+//    order, so every wave of every workgroup obtains the same bits without a broadcast.
+//    At the start of round r a workgroup empties its slot of round r-2 (every workgroup has
+//    finished reading it: they all published round r-1); the store is performed before the
+//    workgroup's next publication (wait count at the start of round r+1).  No cache flush.
+// Waits are bounded.  A wave that times out records the sticky error and clears the
+// workgroup's LDS alive flag; the workgroup agrees on it after its next barrier and every
+// wave then leaves the kernel together.
 constexpr unsigned long long kEmpty = 0x7ff4deadbeef1234ull;
 constexpr int kRing = 8;
+constexpr unsigned long long kSpinLimit = 1ull << 26;
+constexpr int kAllWavePoll = 64;
 
 __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroup sum with one barrier: red holds two 16-entry halves used alternately (a half
+// is rewritten only after the barrier of the other half has been passed by every wave).
+__device__ __forceinline__ double block_sum2(double v, double* red, unsigned& sel) {
+  double* rb = red + (sel & 1u) * 16;
+  sel ^= 1u;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) rb[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) s += rb[i];
+  return s;
 }
 
 struct GridTeam {
@@ -516,30 +536,29 @@ struct GridTeam {
   unsigned long long gen;
   unsigned rnd;
   bool dead;
+  unsigned sel;                // alternating half of the reduction scratch
 
-  __device__ void timeout() {
+  __device__ void timeout(int* lds_flag) {
+    *lds_flag = 0;
     atomicCAS(err, 0, kErrDevice);
   }
 
   __device__ bool sync(int* lds_flag) {
     __syncthreads();
+    if (*lds_flag == 0) { dead = true; return false; }
     if (G == 1) return true;
     gen += 1;
     if (threadIdx.x == 0) {
-      *lds_flag = 1;
       __threadfence();
       st_agent(&flags[rank], gen);
     }
-    __syncthreads();
-    bool ok = true;
     for (int i = threadIdx.x; i < G; i += blockDim.x) {
       unsigned long long spins = 0;
       while (ld_agent(&flags[i]) < gen) {
         __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1ull << 26)) { ok = false; break; }
+        if (++spins > kSpinLimit) { timeout(lds_flag); break; }
       }
     }
-    if (!ok) { *lds_flag = 0; timeout(); }
     __syncthreads();
     if (threadIdx.x == 0) __threadfence();
     __syncthreads();
@@ -547,42 +566,76 @@ struct GridTeam {
     return true;
   }
 
-  // all-reduce of one double per workgroup; fixed summation order on every workgroup.
-  // fenced = true also publishes this workgroup's earlier global stores and makes the other
-  // workgroups' ones visible (release before the partial, acquire after the slots): used
-  // where bulk data written before the reduction is gathered across slices afterwards.
-  __device__ double allreduce(double partial, double* red, int* lds_flag, bool fenced = false) {
-    if (threadIdx.x == 0) *lds_flag = 1;   // ordered before the polls by block_sum's barriers
-    const double p = block_sum(partial, red);
+  // Publish this workgroup's partial of the current round; returns the workgroup sum.
+  // fenced = true also releases this workgroup's earlier global stores (see wait()).
+  __device__ double post(double partial, double* red, int* lds_flag, bool fenced) {
+    const double p = block_sum2(partial, red, sel);
+    if (*lds_flag == 0) { dead = true; return 0.0; }
     if (G == 1) return p;
-    unsigned long long* slot = ring + (size_t)(rnd % kRing) * G;
     if (threadIdx.x == 0) {
       if (fenced) __threadfence();
-      st_agent(&slot[rank], p == p ? (unsigned long long)__double_as_longlong(p) : 0x7ff8000000000000ull);
+      __builtin_amdgcn_s_waitcnt(0);
+      if (rnd >= 2) st_agent(&ring[(size_t)((rnd - 2) % kRing) * G + rank], kEmpty);
+      st_agent(&ring[(size_t)(rnd % kRing) * G + rank],
+               p == p ? (unsigned long long)__double_as_longlong(p) : 0x7ff8000000000000ull);
     }
-    double v = 0.0;
-    bool ok = true;
-    for (int i = threadIdx.x; i < G; i += blockDim.x) {
-      unsigned long long x, spins = 0;
-      while ((x = ld_agent(&slot[i])) == kEmpty) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins > (1ull << 26)) { ok = false; break; }
+    return p;
+  }
+
+  // Sum of the round's G partials, identical bits in every wave.  fenced = true acquires
+  // after every slot has been observed, so that bulk data released by the other
+  // workgroups before their post() is visible afterwards.
+  __device__ double wait(double p, int* lds_flag, bool fenced, double* red = nullptr) {
+    if (G == 1 || dead) return p;
+    const unsigned long long* slot = ring + (size_t)(rnd % kRing) * G;
+    double tot;
+    // small teams: every wave polls all slots (no broadcast barrier); large teams: wave 0
+    // polls and broadcasts through LDS, keeping the polling traffic on the ring lines low
+    const bool all_waves = G <= kAllWavePoll || red == nullptr;
+    if (all_waves) {
+      double s = 0.0;
+      for (int i = (threadIdx.x & 63); i < G; i += 64) {
+        unsigned long long x, spins = 0;
+        while ((x = ld_agent(&slot[i])) == kEmpty) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) { timeout(lds_flag); break; }
+        }
+        s += __longlong_as_double((long long)x);
       }
-      v += __longlong_as_double((long long)x);
+      tot = wave_sum(s);
+    } else {
+      // one slot per thread over the first ceil(G/64) waves, then a fixed-order wave sum
+      double s = 0.0;
+      for (int i = threadIdx.x; i < G; i += blockDim.x) {
+        unsigned long long x, spins = 0;
+        while ((x = ld_agent(&slot[i])) == kEmpty) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kSpinLimit) { timeout(lds_flag); break; }
+        }
+        s += __longlong_as_double((long long)x);
+      }
+      s = wave_sum(s);
+      double* rb = red + (sel & 1u) * 16;
+      sel ^= 1u;
+      if ((threadIdx.x & 63) == 0) rb[threadIdx.x >> 6] = s;
+      __syncthreads();
+      tot = 0.0;
+      const int nw = (blockDim.x + 63) >> 6;
+      for (int w = 0; w < nw; ++w) tot += rb[w];
     }
-    if (!ok) { *lds_flag = 0; timeout(); }
-    if (fenced) {             // acquire after every slot has been observed
+    if (fenced) {
       __syncthreads();
       if (threadIdx.x == 0) __threadfence();
-    }
-    const double tot = block_sum(v, red);
-    if (threadIdx.x == 0 && rnd >= 2) {
-      st_agent(&ring[(size_t)((rnd - 2) % kRing) * G + rank], kEmpty);
-      __builtin_amdgcn_s_waitcnt(0);   // the emptying store is performed before any later store
+      __syncthreads();
+      if (*lds_flag == 0) dead = true;
     }
     rnd += 1;
-    if (*lds_flag == 0) { dead = true; return 0.0; }
     return tot;
+  }
+
+  __device__ double allreduce(double partial, double* red, int* lds_flag, bool fenced = false) {
+    const double p = post(partial, red, lds_flag, fenced);
+    return wait(p, lds_flag, fenced, red);
   }
 };
 

@@ -370,13 +370,15 @@ __global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
   double* lw = lds;
   double* lv = lds + C;
   double* red = lv + C;
-  double* yb = red + 16;
+  double* yb = red + 32;
   int* flag = (int*)(yb + kMaxM);
-  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false};
+  if (threadIdx.x == 0) *flag = 1;   // workgroup alive flag (cleared on a synchronisation timeout)
+  __syncthreads();
+  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false, 0u};
   expv_body<T, MODEL>(tm, A, lw, lv, red, yb, flag);
 }
 
-size_t expv_lds_bytes(int chunk) { return (size_t)(2 * chunk + 16 + kMaxM) * sizeof(double) + 16 * sizeof(int); }
+size_t expv_lds_bytes(int chunk) { return (size_t)(2 * chunk + 32 + kMaxM) * sizeof(double) + 16 * sizeof(int); }
 
 template <typename T, int MODEL>
 static const void* expv_fn() {

@@ -27,7 +27,22 @@ struct BlockTeam {
     return true;
   }
   __device__ double allreduce(double p, double* red, int*, bool = false) { return block_sum(p, red); }
+  __device__ double post(double p, double* red, int*, bool) { return block_sum(p, red); }
+  __device__ double wait(double p, int*, bool, double* = nullptr) { return p; }
 };
+
+// Entries of the next basis vector's slice that a thread can hold in registers while a
+// reduction is in flight (a slice of up to kPF * blockDim entries); larger windows push
+// the kernel's register allocation into spills.
+constexpr int kPF = 4;
+
+__device__ __forceinline__ void prefetch_row(double (&pf)[kPF], const double* row, int nloc) {
+#pragma unroll
+  for (int r = 0; r < kPF; ++r) {
+    const int t = threadIdx.x + r * blockDim.x;
+    if (t < nloc) pf[r] = row[t];
+  }
+}
 
 struct ProjResult {
   int m;
@@ -41,6 +56,25 @@ struct ProjResult {
 
 __device__ __forceinline__ int read_err(const int* err) {
   return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Element forces of this team member's elements (operator apply, part 1).
+template <typename T, int MODEL>
+__device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, const double* src,
+                                                         double hinv, T* F, int rank, int G) {
+  bool okA = true;
+  if (elem_lanes<T, MODEL>() == 8) {
+    // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
+    for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
+      okA &= elem_force_qp<T, MODEL>(M, op, e, src, hinv, true, F);
+  } else {
+    for (int e = rank * blockDim.x + threadIdx.x; e < M.n_elems; e += G * blockDim.x) {
+      T fe[8][3];
+      okA &= elem_force<T, MODEL>(M, op, e, src, hinv, true, fe);
+      store_force(M, e, fe, F);
+    }
+  }
+  return okA;
 }
 
 // X <- exp(f A) X on entry ||X|| = beta.  Every workgroup returns the same result.
@@ -70,18 +104,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
   for (int j = 1; j <= mcap; ++j) {
     // ---- operator apply, part 1: element forces of the u-part of v_{j-1}
-    bool okA = true;
-    if (elem_lanes<T, MODEL>() == 8) {
-      // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
-      for (int e = (tm.rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (tm.G * blockDim.x) >> 3)
-        okA &= elem_force_qp<T, MODEL>(M, A.op, e, src, hinv, true, F);
-    } else {
-      for (int e = tm.rank * blockDim.x + threadIdx.x; e < M.n_elems; e += tm.G * blockDim.x) {
-        T fe[8][3];
-        okA &= elem_force<T, MODEL>(M, A.op, e, src, hinv, true, fe);
-        store_force(M, e, fe, F);
-      }
-    }
+    const bool okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G);
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;
     {
@@ -109,7 +132,14 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
       lv[i] = v0;
       part += w * v0;
     }
-    double h = tm.allreduce(part, red, flag);
+    // the next basis slice is loaded while each reduction is in flight
+    // prefetch only in the linear kernels (reduction-latency bound); the secant-material
+    // kernels need those registers for their element code
+    const bool pf_ok = (MODEL == kLinear) && nloc <= kPF * (int)blockDim.x;
+    double pf[kPF];
+    double hp = tm.post(part, red, flag, false);
+    if (pf_ok && 1 < j) prefetch_row(pf, W.V + Lp + c0, nloc);
+    double h = tm.wait(hp, flag, false, red);
     if (tm.dead) return R;
     if (lead && threadIdx.x == 0) W.H[0 * ldH + (j - 1)] = h;
     hmax = fmax(hmax, fabs(h));
@@ -119,15 +149,30 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     for (int i = 1; i <= j; ++i) {
       part = 0.0;
       if (i < j) {
-        const double* Vi = W.V + (size_t)i * Lp + c0;
-        for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-          const double w = lw[t] - hprev * lv[t];
-          lw[t] = w;
-          const double vi = Vi[t];
-          lv[t] = vi;
-          part += w * vi;
+        if (pf_ok) {
+#pragma unroll
+          for (int r = 0; r < kPF; ++r) {
+            const int t = threadIdx.x + r * blockDim.x;
+            if (t < nloc) {
+              const double w = lw[t] - hprev * lv[t];
+              lw[t] = w;
+              lv[t] = pf[r];
+              part += w * pf[r];
+            }
+          }
+        } else {
+          const double* Vi = W.V + (size_t)i * Lp + c0;
+          for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+            const double w = lw[t] - hprev * lv[t];
+            lw[t] = w;
+            const double vi = Vi[t];
+            lv[t] = vi;
+            part += w * vi;
+          }
         }
-        h = tm.allreduce(part, red, flag);
+        hp = tm.post(part, red, flag, false);
+        if (pf_ok && i + 1 < j) prefetch_row(pf, W.V + (size_t)(i + 1) * Lp + c0, nloc);
+        h = tm.wait(hp, flag, false, red);
         if (tm.dead) return R;
         if (lead && threadIdx.x == 0) W.H[(size_t)i * ldH + (j - 1)] = h;
         hmax = fmax(hmax, fabs(h));

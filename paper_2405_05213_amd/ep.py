@@ -44,6 +44,7 @@ _SIGS = {
     "ep_set_krylov": [_vp, _dbl, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dbl],
     "ep_set_precision": [_vp, C.c_int],
     "ep_set_launch": [_vp, C.c_int],
+    "ep_autotune": [_vp, _dbl, C.c_int, C.c_int, _P(C.c_int), _P(_dbl)],
     "ep_workspace_size": [_vp, _P(C.c_size_t)],
     "ep_bind_workspace": [_vp, _vp, C.c_size_t],
     "ep_set_state": [_vp, _dbl, _vp, _vp],
@@ -159,6 +160,11 @@ class Context:
 
     def set_launch(self, workgroups: int):
         self._call("ep_set_launch", int(workgroups))
+
+    def autotune(self, dt, m_trial=16, trials=3):
+        g, ms = C.c_int(), C.c_double()
+        self._call("ep_autotune", float(dt), int(m_trial), int(trials), C.byref(g), C.byref(ms))
+        return g.value, ms.value
 
     def workspace_size(self) -> int:
         n = C.c_size_t()

@@ -31,12 +31,26 @@ def summarize(db: str, top: int = 15):
     return "\n".join(out)
 
 
+def counters(db: str, top: int = 15):
+    """Average value per dispatch of every collected counter, per kernel (rocprofv3 --pmc)."""
+    con = sqlite3.connect(db)
+    rows = con.execute(
+        "select kernel_name, counter_name, count(distinct dispatch_id), avg(value), min(value), max(value) "
+        "from counters_collection group by kernel_name, counter_name order by avg(value) desc").fetchall()
+    out = [f"{'kernel':<70} {'counter':<14} {'dispatches':>10} {'avg':>16} {'min':>16} {'max':>16}"]
+    for r in rows[: top * 4]:
+        name = r[0] if len(r[0]) <= 70 else r[0][:67] + "..."
+        out.append(f"{name:<70} {r[1]:<14} {r[2]:>10d} {r[3]:>16.1f} {r[4]:>16.1f} {r[5]:>16.1f}")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db")
     ap.add_argument("--top", type=int, default=15)
+    ap.add_argument("--counters", action="store_true", help="summarise PMC counters instead of durations")
     a = ap.parse_args()
-    print(summarize(a.db, a.top))
+    print(counters(a.db, a.top) if a.counters else summarize(a.db, a.top))
 
 
 if __name__ == "__main__":
