@@ -81,6 +81,33 @@ def algorithmic_bytes(prob, m, k, s_x=8, projections=1):
     return projections * k * per_proj
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expv_c2_linear_f64_traffic.json")
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2405_05213_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(config_name, precision, m, k, workgroups):
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3 counter runs
+    (FETCH_SIZE / WRITE_SIZE scaled by a copy kernel of known size), or None when the kernel
+    sources or the launch configuration differ from the profiled ones."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    same = (rec.get("kernel_sources_sha256") == kernel_sources_sha256()
+            and rec.get("config") == config_name and rec.get("precision") == precision
+            and rec.get("m") == m and rec.get("k") == k and rec.get("workgroups") == workgroups)
+    return float(rec["traffic_bytes_per_launch"]) if same else None
+
+
 def energy_err(e0, e1):
     E0 = e0[0] + e0[1] - e0[2]
     E1 = e1[0] + e1[1] - e1[2]
@@ -220,7 +247,8 @@ def main():
         "roofline": {
             "kernel": "k_expv (persistent Arnoldi-MGS projection incl. operator applies), one launch per step",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(args.config, args.precision, m_used, k_used, head["workgroups"]),
             "alg_bytes_per_launch": alg, "avg_launch_ms": launch_s * 1e3,
         },
     }
