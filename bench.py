@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--m-max", type=int, default=64)
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed_f32"])
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--ortho", type=int, default=-1, choices=[-1, 0, 1],
+                    help="Gram-Schmidt form: -1 automatic, 0 sequential, 1 compact WY")
     ap.add_argument("--adaptive", action="store_true", help="keep the adaptive subspace choice while timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
@@ -133,7 +135,7 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
     """Calibrate m on the warm-up steps, then time `steps` steps with m (and k) fixed."""
     from paper_2405_05213_amd import solver_from_problem
     cal = solver_from_problem(prob, m_max=m_max, precision=precision, workgroups=workgroups,
-                              stream=stream.cuda_stream)
+                              stream=stream.cuda_stream, ortho=args.ortho)
     nwarm = max(1, warmup)
     cal.step(prob.dt, nwarm)
     cal.sync()
@@ -150,7 +152,8 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
     else:
         del cal
         ctx = solver_from_problem(prob, m_max=m_max, m_fixed=max(m_cal, m_pred), k_fixed=k_cal,
-                                  precision=precision, workgroups=tuned_G, stream=stream.cuda_stream)
+                                  precision=precision, workgroups=tuned_G, stream=stream.cuda_stream,
+                                  ortho=args.ortho)
         ctx.step(prob.dt, nwarm)
     ctx.sync()
     e_ref = ctx.energy() if prob.model == "linear" else (0.0, 0.0, 0.0)
@@ -171,6 +174,7 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
         "dof_matvecs_per_s": prob.n_free * mv / gpu_s, "m": st1["m"], "k": st1["k"],
         "m_fixed": max(m_cal, m_pred), "energy_rel_err": energy_err(e_ref, e1) if prob.model == "linear" else None,
         "matvecs": mv, "wall_s": wall, "step_ms": ms, "ctx": ctx, "workgroups": tuned_G,
+        "ortho": ctx.orthogonalization(),
     }
 
 
@@ -241,6 +245,7 @@ def main():
             "dt": prob.dt, "m": m_used, "substeps": k_used,
             "m_mode": "adaptive" if args.adaptive else "calibrated then fixed",
             "precision": args.precision, "free_dofs": prob.n_free, "workgroups": head["workgroups"],
+            "gram_schmidt": "compact-WY MGS" if head["ortho"] == 1 else "sequential MGS",
         },
         "time_steps_per_s": head["time_steps_per_s"],
         "energy_rel_err": head["energy_rel_err"],

@@ -118,6 +118,18 @@ ep_status ep_set_krylov(ep_ctx* ctx, double tol, int m_max, int check_every, int
 
 ep_status ep_set_precision(ep_ctx* ctx, ep_precision prec);
 
+/* Form of the Arnoldi modified Gram-Schmidt loop (Sec. 4.3) in the single-instance kernel,
+ * set before ep_bind_workspace.  mode 0: sequential, one team reduction per inner
+ * product (j + 1 in step j).  mode 1: compact WY, the same recurrence written as the
+ * triangular solve (I + L_j) h = V_j^T w with L_j the strictly lower triangle of V_j^T V_j;
+ * one vector reduction of the 2j - 1 inner products plus the norm per step; needs
+ * m_max <= 64 (else EP_ERR_ARG at ep_workspace_size / ep_bind_workspace).  mode -1
+ * (default): 1 when m_max <= 64, else 0.  Batches always use mode 0 (one workgroup per
+ * instance).  Both forms give the same H and V up to rounding. */
+ep_status ep_set_orthogonalization(ep_ctx* ctx, int mode);
+/* The form in effect (after binding) or that binding would choose. */
+ep_status ep_get_orthogonalization(ep_ctx* ctx, int* mode);
+
 /* Number of workgroups of the persistent Krylov kernel (0 = automatic). */
 ep_status ep_set_launch(ep_ctx* ctx, int workgroups);
 
@@ -164,6 +176,13 @@ ep_status ep_get_energy(ep_ctx* ctx, double* kinetic, double* strain, double* ex
  * and |s - s0| before the reset of the augmented entry. */
 ep_status ep_get_stats(ep_ctx* ctx, int64_t* matvecs, int* last_m, double* last_eps,
                        int* last_k, double* aug_drift);
+
+/* Launch layout of the persistent Krylov kernel after binding (or autotuning): the
+ * number of workgroups, the Krylov-vector entries each owns, and whether the mesh was
+ * found congruent (every element a translate of element 0: J^{-1} and det J agree to
+ * 1e-13 at every quadrature point), which selects the stored-element-stiffness path of the
+ * linear-elastic operator. */
+ep_status ep_get_launch(ep_ctx* ctx, int* workgroups, int* chunk, int* congruent);
 
 /* Per-step log of the last n steps (n <= 4096): m of the corrector and predictor
  * projections (first substep), substep counts and eps.  Arrays of length n. */

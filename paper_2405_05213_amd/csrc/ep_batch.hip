@@ -24,7 +24,7 @@ static __device__ __forceinline__ int free_slot(int a, int b) {
 // One step of one instance (Sec. 4.1-4.2); returns false after a sticky error.
 template <typename T, int MODEL, class Team>
 __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double dt, double* lw, double* lv,
-                            double* red, double* yb, int* flag) {
+                            double* red, double* yb, int* flag, const KLds& X) {
   ExpvArgs a;
   a.M = B.M;
   a.W = B.W;
@@ -40,7 +40,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double
     a.x_in = B.S;
     a.x_out = B.S;
     a.out_mode = 0;
-    expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag);
+    expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag, X);
   } else {
     OpArgs pred{};
     pred.tau = 0.5 * dt;
@@ -70,7 +70,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double
     a.x_in = B.S;
     a.x_out = B.hist + (size_t)snew * n3;
     a.out_mode = 1;
-    expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag);
+    expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag, X);
     if (tm.dead || read_err(&B.W.ctrl->err) != 0) return false;
     OpArgs corr{};
     corr.tau = dt;
@@ -83,7 +83,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double
     a.x_in = B.S;
     a.x_out = B.S;
     a.out_mode = 0;
-    expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag);
+    expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag, X);
     if (B.nhist == 0) {
       B.hist_old = -1;
       B.hist_new = snew;
@@ -100,15 +100,19 @@ __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double
   return true;
 }
 
-constexpr int kBatchHead = 32 + kMaxM + 16;   // doubles of LDS before the slice buffers
+// doubles of LDS before the slice buffers: red[32] | yb[kMaxM] | ints flag[16], ired[16]
+constexpr int kBatchHead = 32 + kMaxM + 16;
 
 template <typename T, int MODEL>
 __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* ids, KrylovCfg cfg, double dt,
-                                                    int n_steps) {
+                                                    int n_steps, int lds_slices) {
   extern __shared__ double lds[];
   double* red = lds;
   double* yb = lds + 32;
   int* flag = (int*)(lds + 32 + kMaxM);
+  // the slice region (lds_slices doubles) doubles as expm scratch: the sequential form
+  // reloads both slice buffers after a check point
+  const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, flag + 16};
   if (threadIdx.x == 0) *flag = 1;
   __syncthreads();
   const int id = ids[blockIdx.x];
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
   }
   BlockTeam tm;
   for (int s = 0; s < n_steps; ++s)
-    if (!device_step<T, MODEL>(tm, B, cfg, dt, lw, lv, red, yb, flag)) break;
+    if (!device_step<T, MODEL>(tm, B, cfg, dt, lw, lv, red, yb, flag, X)) break;
   if (threadIdx.x == 0) {
     tab[id].t = B.t;
     tab[id].step_idx = B.step_idx;
@@ -157,7 +161,8 @@ hipError_t launch_batch(BatchInst* tab, const int* ids, int count, int model, co
   KrylovCfg c = cfg;
   double d = dt;
   int n = n_steps;
-  void* args[] = {&tab, &ids, &c, &d, &n};
+  int ls = 2 * max_lds_chunk;
+  void* args[] = {&tab, &ids, &c, &d, &n, &ls};
   return hipLaunchKernel(fn, dim3(count), dim3(kThreads), args, lds, st);
 }
 

@@ -21,6 +21,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr long long kMaxChunk = 9984;     // (2 * 9984 + 304) doubles of LDS fit in 160 KB
+constexpr long long kLdsBytes = 160 * 1024;
 
 struct Layout {
   size_t off = 0;
@@ -52,7 +53,7 @@ struct Inst {
   int n3 = 0, L = 0, Lp = 0;
   // workspace offsets
   size_t o_xyz, o_conn, o_incp, o_inc, o_geo, o_geo32, o_vdet, o_mih, o_mh, o_p0, o_p0bar, o_faces, o_fincp,
-      o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y,
+      o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y, o_ke,
       o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr;
   Mesh M{};
   KWork W{};
@@ -75,7 +76,8 @@ struct ep_ctx {
   bool mesh_set = false, material_set = false;
   Inst one;
   std::vector<Inst> insts;
-  KrylovCfg cfg{1e-10, 64, 4, 0, 0, 64, 0};
+  KrylovCfg cfg{1e-10, 64, 4, 0, 0, 64, 0, 0};
+  int ortho_user = -1;                  // -1: automatic
   double s0_user = -1.0;
   int G_user = 0;
   int cus = 0;
@@ -183,11 +185,27 @@ static void fill_traction(Inst& I, int64_t n_faces, const int32_t* fn, const dou
 }
 
 // ------------------------------------------------------------------------------ layout
+// Orthogonalisation form of the single-instance kernel: compact WY (one vector reduction
+// per Arnoldi step) unless asked otherwise or the subspace exceeds its LDS triangle.
+static int eff_ortho(const ep_ctx* c) {
+  if (c->batch) return 0;
+  if (c->ortho_user >= 0) return c->ortho_user;
+  return c->cfg.m_max <= kMaxCwyM ? 1 : 0;
+}
+
+// Largest Krylov-vector slice per workgroup: two slices of it share the LDS with the
+// reduction scratch (and T of the compact-WY form).
+static long long max_chunk(const ep_ctx* c) {
+  const long long fixed = (long long)expv_lds_head_bytes(c->cfg.ortho, c->cfg.m_max);
+  return std::max(0LL, (kLdsBytes - fixed) / 16 / 64 * 64);
+}
+
 static int pick_G(const ep_ctx* c, const Inst& I, int* chunk) {
   const int maxG = std::max(1, c->cus);
   // the workgroup's slice of the Arnoldi vector (and of the previous basis vector) lives in
-  // LDS: at most kMaxChunk entries per workgroup
-  const int Gmin = (int)((I.Lp + kMaxChunk - 1) / kMaxChunk);
+  // LDS: at most max_chunk entries per workgroup
+  const long long mc = std::max(64LL, max_chunk(c));
+  const int Gmin = (int)((I.Lp + mc - 1) / mc);
   int G = c->G_user > 0 ? c->G_user : (int)std::min<long long>(maxG, std::max<long long>(1, (I.Lp + 2047) / 2048));
   G = std::max(G, Gmin);
   G = std::max(1, std::min(G, std::min(I.Lp / 64 > 0 ? I.Lp / 64 : 1, 1024)));
@@ -225,7 +243,9 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_F32 = L.take(4 * 24 * ne);
   I.o_hist = L.take(8 * 3 * n3);
   I.o_stage = L.take(8 * 2 * n3);
-  I.o_slots = L.take(8 * 9 * (size_t)std::max(Gmax, 1));   // G barrier flags + 8 G ring slots
+  // G barrier flags + 8 G ring slots (+ 8 G vector slots of 2 m_max values)
+  const size_t vw = c->cfg.ortho == 1 ? 2 * mm : 0;
+  I.o_slots = L.take(8 * (1 + kRing + kRing * vw) * (size_t)std::max(Gmax, 1));
   I.o_H = L.take(8 * (mm + 1) * mm);
   I.o_Escr = L.take(8 * 9 * mm * mm);     // 8 m^2 expm work + m^2 output staging
   I.o_y = L.take(8 * (mm + 1));
@@ -236,6 +256,7 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_eout = L.take(8 * 4);
   I.o_flags = L.take(4 * 4);
   I.o_wscr = L.take(c->batch ? 8 * 2 * Lp : 8);
+  I.o_ke = L.take(12 * 24 * kKeLd);
 }
 
 static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
@@ -350,6 +371,14 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   for (int i = 0; i < 4; ++i) M.mp[i] = I.mp[i];
   M.s0 = auto_s0(c, I);
   M.s_inv = M.s0 != 0.0 ? 1.0 / M.s0 : 0.0;
+  M.ke = nullptr;
+  M.ke32 = nullptr;
+  if (M.congruent && I.n_elems > 0) {
+    launch_stiffness(M, dptr<double>(c, I.o_ke), reinterpret_cast<float*>(dptr<double>(c, I.o_ke) + 24 * kKeLd), st);
+    EP_HIP(c, hipGetLastError());
+    M.ke = dptr<double>(c, I.o_ke);
+    M.ke32 = reinterpret_cast<const float*>(M.ke + 24 * kKeLd);
+  }
   KWork& W = I.W;
   W.V = dptr<double>(c, I.o_V);
   W.Wun = dptr<double>(c, I.o_Wun);
@@ -358,6 +387,8 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   W.F32 = dptr<float>(c, I.o_F32);
   W.flags = dptr<unsigned long long>(c, I.o_slots);
   W.ring = W.flags + std::max(Gslots, 1);
+  W.vw = c->cfg.ortho == 1 ? 2 * c->cfg.m_max : 0;
+  W.vring = W.vw > 0 ? W.ring + (size_t)kRing * std::max(Gslots, 1) : nullptr;
   W.H = dptr<double>(c, I.o_H);
   W.Escr = dptr<double>(c, I.o_Escr);
   W.y = dptr<double>(c, I.o_y);
@@ -593,6 +624,20 @@ ep_status ep_set_krylov(ep_ctx* c, double tol, int m_max, int check_every, int m
   return EP_OK;
 }
 
+ep_status ep_set_orthogonalization(ep_ctx* c, int mode) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "ep_set_orthogonalization after ep_bind_workspace");
+  if (mode < -1 || mode > 1) return fail(c, EP_ERR_ARG, "orthogonalisation mode must be -1, 0 or 1");
+  c->ortho_user = mode;
+  return EP_OK;
+}
+
+ep_status ep_get_orthogonalization(ep_ctx* c, int* mode) {
+  if (!c || !mode) return EP_ERR_ARG;
+  *mode = c->bound ? c->cfg.ortho : eff_ortho(c);
+  return EP_OK;
+}
+
 ep_status ep_set_precision(ep_ctx* c, ep_precision p) {
   if (!c) return EP_ERR_ARG;
   if (p != EP_PREC_F64 && p != EP_PREC_MIXED_F32) return fail(c, EP_ERR_ARG, "unknown precision");
@@ -613,6 +658,11 @@ ep_status ep_workspace_size(ep_ctx* c, size_t* bytes) {
   if (!c->batch && (!c->mesh_set || !c->material_set))
     return fail(c, EP_ERR_ORDER, "workspace size needs the mesh and the material");
   if (c->batch && c->insts.empty()) return fail(c, EP_ERR_ORDER, "batch has no instances");
+  if (!c->bound) {
+    if (!c->batch && c->ortho_user == 1 && c->cfg.m_max > kMaxCwyM)
+      return fail(c, EP_ERR_ARG, "compact-WY orthogonalisation needs m_max <= 64");
+    c->cfg.ortho = eff_ortho(c);
+  }
   *bytes = plan_all(c);
   return EP_OK;
 }
@@ -641,7 +691,7 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
     // cooperative residency: shrink G until it fits
     int bpc = 0;
     for (;;) {
-      EP_HIP(c, expv_max_blocks(c->cfg.prec, c->one.model, chunk, &bpc));
+      EP_HIP(c, expv_max_blocks(c->cfg, c->one.model, chunk, &bpc));
       if ((long long)bpc * c->cus >= G || G == 1) break;
       G = std::max(1, (int)((long long)bpc * c->cus));
       chunk = ((c->one.Lp + G - 1) / G + 63) / 64 * 64;
@@ -756,6 +806,15 @@ ep_status ep_get_stats(ep_ctx* c, int64_t* matvecs, int* last_m, double* last_ep
   if (last_eps) *last_eps = h.ks[0].last_eps;
   if (last_k) *last_k = h.ks[0].last_k;
   if (drift) *drift = h.drift;
+  return EP_OK;
+}
+
+ep_status ep_get_launch(ep_ctx* c, int* workgroups, int* chunk, int* congruent) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (workgroups) *workgroups = c->one.W.G;
+  if (chunk) *chunk = c->one.W.chunk;
+  if (congruent) *congruent = c->one.M.congruent;
   return EP_OK;
 }
 
@@ -957,9 +1016,9 @@ ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G
   for (int G : cand) {
     if (G > Gslots || G > std::max(1, I.Lp / 64)) continue;
     int chunk = ((I.Lp + G - 1) / G + 63) / 64 * 64;
-    if (chunk > kMaxChunk) continue;
+    if (chunk > max_chunk(c)) continue;
     int bpc = 0;
-    if (expv_max_blocks(c->cfg.prec, I.model, chunk, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
+    if (expv_max_blocks(c->cfg, I.model, chunk, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
     a.W.G = G;
     a.W.chunk = chunk;
     if (launch_expv(a, c->cfg.prec, c->stream) != hipSuccess) continue;   // warm-up

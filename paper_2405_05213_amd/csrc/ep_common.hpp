@@ -10,6 +10,9 @@ constexpr int kThreads = 512;        // workgroup size of every persistent / ele
 constexpr int kMaxM = 256;           // largest Krylov subspace
 constexpr int kLogSteps = 4096;      // per-step statistics ring
 constexpr int kMaxKnots = 4096;
+constexpr int kMaxCwyM = 64;         // largest subspace of the compact-WY orthogonalisation
+constexpr int kRing = 8;
+constexpr int kKeLd = 25;            // row stride of the stored element stiffness             // rounds of all-reduce slots of a workgroup team
 
 // material ids (ep_model)
 constexpr int kLinear = 0, kNH = 1, kYeoh = 2;
@@ -28,6 +31,8 @@ struct Mesh {
   const double* geo;          // per quadrature point: Jinv (3x3 row major) + w*detJ
   const float* geo32;
   int congruent;              // 1: one geometry set shared by all elements
+  const double* ke;           // congruent meshes: rest-state element stiffness (24 x kKeLd)
+  const float* ke32;          //   and its FP32 rounding; null otherwise
   const double* mih;          // M^{-1/2} per DOF (0 on clamped DOFs)
   const double* mh;           // M^{1/2}  per DOF (0 on clamped DOFs)
   const double* p0bar;        // M^{-1/2} P0 per DOF (0 on clamped DOFs)
@@ -52,6 +57,8 @@ struct KrylovCfg {
   double tol;
   int m_max, check_every, m_fixed, k_fixed, max_substeps;
   int prec;                   // 0 FP64, 1 FP32 element kernels
+  int ortho;                  // 0: one team reduction per projection (sequential MGS);
+                              // 1: MGS in compact-WY form, one vector reduction per step
 };
 
 // Per-projection-kind adaptive state (kept on device between launches).
@@ -93,6 +100,8 @@ struct KWork {
   float* F32;
   unsigned long long* flags;  // G barrier generations
   unsigned long long* ring;   // 8 * G all-reduce slots
+  unsigned long long* vring;  // 8 * G * vw vector all-reduce slots (compact-WY MGS)
+  int vw;                     // row width of a vector slot (2 * m_max)
   double* H;                  // (m_max+1) x m_max Hessenberg (row major, stride m_max)
   double* Escr;               // expm scratch 8 * m_max^2 (+ m_max^2 output staging)
   double* y;                  // m_max coefficients
@@ -101,6 +110,7 @@ struct KWork {
   int G;                      // workgroups of the team
   int chunk;                  // Krylov-vector entries owned by each workgroup
   double* wscr;               // 2 * Lp: slice buffers in device memory when they exceed LDS
+  int ex_cap;                 // doubles of LDS the check point may use for exp(H) (set per launch)
 };
 
 // Device-side record of one instance of a batch: the stepping state lives on the device so

@@ -438,12 +438,85 @@ __device__ __forceinline__ void store_force(const Mesh& M, int e, const T (&f)[8
     for (int i = 0; i < 3; ++i) F[((size_t)a * M.n_elems + e) * 3 + i] = f[a][i];
 }
 
+// Stiffness of the reference element of a congruent mesh at the rest state (the linear
+// branch of elem_force applied to unit vectors): column c = 3b + j of K_e is the element
+// force of the unit displacement of node b in direction j.  Ke row stride kKeLd (odd, so
+// that the 8 lanes of an element read distinct LDS banks).
+
+__device__ __forceinline__ void ke_column(const Mesh& M, int c, double* Ke) {
+  double x[8][3], f[8][3];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      x[a][i] = (3 * a + i == c) ? 1.0 : 0.0;
+      f[a][i] = 0.0;
+    }
+  double lam, mu;
+  rest_lame(M.model, M.mp, lam, mu);
+  for (int q = 0; q < 8; ++q) {
+    const QFactors<double> Q(q);
+    double Jinv[9];
+    for (int k = 0; k < 9; ++k) Jinv[k] = M.geo[(size_t)q * 10 + k];
+    const double wdet = M.geo[(size_t)q * 10 + 9];
+    double X[3][3], S[3][3];
+    grad_at(Q, x, Jinv, X);
+    const double tr = X[0][0] + X[1][1] + X[2][2];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) S[i][k] = mu * (X[i][k] + X[k][i]) + (i == k ? lam * tr : 0.0);
+    scatter_at(Q, S, Jinv, wdet, f);
+  }
+  for (int a = 0; a < 8; ++a)
+    for (int i = 0; i < 3; ++i) Ke[(3 * a + i) * kKeLd + c] = f[a][i];
+}
+
+// Element forces F = K_e x_e of a congruent mesh with K_e in LDS: eight lanes per element,
+// lane a owns node a, loads its three inputs and obtains the other 21 by shuffles.
+// Every lane of the 8-lane group must call with the same e.
+template <typename T>
+__device__ __forceinline__ void elem_force_ke(const Mesh& M, int e, const double* src, double srcscale,
+                                              const T* Ke, T* F) {
+  const int lane = threadIdx.x & 63;
+  const int a = lane & 7, base = lane & ~7;
+  const int nd = M.conn[(size_t)e * 8 + a];
+  T xa[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const size_t d = (size_t)nd * 3 + i;
+    xa[i] = T(src[d] * srcscale * M.mih[d]);
+  }
+  T xe[24];
+#pragma unroll
+  for (int b = 0; b < 8; ++b)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) xe[3 * b + i] = __shfl(xa[i], base + b, 64);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T* row = Ke + (3 * a + i) * kKeLd;
+    T s = T(0);
+#pragma unroll
+    for (int c = 0; c < 24; ++c) s += row[c] * xe[c];
+    F[((size_t)a * M.n_elems + e) * 3 + i] = s;
+  }
+}
+
 // sum of element-slot forces of DOF 3*A + c over the elements around node A
+// (slot indices, then forces, are loaded 8 at a time so that the loads overlap)
 template <typename T>
 __device__ __forceinline__ double gather_force(const Mesh& M, const T* F, int A, int c) {
   double s = 0.0;
-  const int p1 = M.inc_ptr[A + 1];
-  for (int p = M.inc_ptr[A]; p < p1; ++p) s += double(F[(size_t)M.inc[p] * 3 + c]);
+  const int p0 = M.inc_ptr[A], p1 = M.inc_ptr[A + 1];
+  for (int p = p0; p < p1; p += 8) {
+    int sl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sl[u] = p + u < p1 ? M.inc[p + u] : -1;
+    T f[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) f[u] = sl[u] >= 0 ? F[(size_t)sl[u] * 3 + c] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (sl[u] >= 0) s += double(f[u]);
+  }
   return s;
 }
 
@@ -503,7 +576,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // workgroup's LDS alive flag; the workgroup agrees on it after its next barrier and every
 // wave then leaves the kernel together.
 constexpr unsigned long long kEmpty = 0x7ff4deadbeef1234ull;
-constexpr int kRing = 8;
 constexpr unsigned long long kSpinLimit = 1ull << 26;
 constexpr int kAllWavePoll = 64;
 
@@ -529,6 +601,7 @@ __device__ __forceinline__ double block_sum2(double v, double* red, unsigned& se
 }
 
 struct GridTeam {
+  static constexpr bool kVecReduce = true;
   int G, rank;
   unsigned long long* flags;   // [G] barrier generations
   unsigned long long* ring;    // [kRing * G] all-reduce slots
@@ -537,6 +610,9 @@ struct GridTeam {
   unsigned rnd;
   bool dead;
   unsigned sel;                // alternating half of the reduction scratch
+  unsigned long long* vring;   // [kRing * G * vw] vector all-reduce slots
+  int vw;
+  unsigned vrnd;
 
   __device__ void timeout(int* lds_flag) {
     *lds_flag = 0;
@@ -636,6 +712,63 @@ struct GridTeam {
   __device__ double allreduce(double partial, double* red, int* lds_flag, bool fenced = false) {
     const double p = post(partial, red, lds_flag, fenced);
     return wait(p, lds_flag, fenced, red);
+  }
+
+  // All-reduce of K <= min(vw, blockDim.x) values.  On entry vals[0..K) holds this
+  // workgroup's partials behind a barrier; on return it holds the team sums, the same bits
+  // in every workgroup (rank-ordered sums).  Same slot protocol as post()/wait(), one slot
+  // entry per value; a thread polls up to 8 entries at once.  gp: blockDim.x doubles of LDS.
+  __device__ bool allreduce_vec(double* vals, int K, double* gp, int* lds_flag) {
+    if (*lds_flag == 0) { dead = true; return false; }
+    if (G == 1) return true;
+    const size_t slot = (size_t)G * vw;
+    unsigned long long* cur = vring + (size_t)(vrnd % kRing) * slot;
+    const size_t row = (size_t)rank * vw;
+    if (vrnd >= 2) {
+      unsigned long long* old = vring + (size_t)((vrnd - 2) % kRing) * slot + row;
+      for (int t = threadIdx.x; t < vw; t += blockDim.x) st_agent(old + t, kEmpty);
+    }
+    for (int t = threadIdx.x; t < K; t += blockDim.x) {
+      const double p = vals[t];
+      st_agent(cur + row + t, p == p ? (unsigned long long)__double_as_longlong(p) : 0x7ff8000000000000ull);
+    }
+    const int Q = (int)blockDim.x / K;          // rank groups per value
+    const int t = threadIdx.x;
+    if (t < Q * K) {
+      const int k = t % K, g = t / K;
+      constexpr int U = 8;
+      double s = 0.0;
+      for (int i0 = g; i0 < G; i0 += U * Q) {
+        unsigned long long x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * Q;
+          x[u] = i < G ? ld_agent(cur + (size_t)i * vw + k) : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int i = i0 + u * Q;
+          unsigned long long spins = 0;
+          while (x[u] == kEmpty) {
+            __builtin_amdgcn_s_sleep(1);
+            x[u] = ld_agent(cur + (size_t)i * vw + k);
+            if (++spins > kSpinLimit) { timeout(lds_flag); break; }
+          }
+          s += __longlong_as_double((long long)x[u]);
+        }
+      }
+      gp[g * K + k] = s;
+    }
+    __syncthreads();
+    if (t < K) {
+      double tot = 0.0;
+      for (int g = 0; g < Q; ++g) tot += gp[g * K + t];
+      vals[t] = tot;
+    }
+    __syncthreads();
+    vrnd += 1;
+    if (*lds_flag == 0) { dead = true; return false; }
+    return true;
   }
 };
 

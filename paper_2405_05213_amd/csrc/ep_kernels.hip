@@ -79,12 +79,21 @@ __global__ void k_geometry(const double* __restrict__ xyz, const int* __restrict
 }
 
 // flag elements whose Gauss-point geometry differs from element 0's
+// An element is congruent to element 0 when every J^{-1} entry agrees to 1e-13 of the
+// largest J^{-1} entry of that quadrature point (entries that vanish in exact arithmetic
+// carry rounding noise) and det J agrees to 1e-13 relative.
 __global__ void k_congruence(const double* __restrict__ geo, int n_e, int* __restrict__ mismatch) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n_e * 80) return;
-  const double g0 = geo[idx % 80];
-  const double g = geo[idx];
-  if (fabs(g - g0) > 1e-13 * fabs(g0) + 1e-300) atomicOr(mismatch, 1);
+  const int r = (int)(idx % 80);
+  const int q = r / 10, k = r - q * 10;
+  double scale = 0.0;
+  if (k < 9) {
+    for (int i = 0; i < 9; ++i) scale = fmax(scale, fabs(geo[q * 10 + i]));
+  } else {
+    scale = fabs(geo[r]);
+  }
+  if (fabs(geo[idx] - geo[r]) > 1e-13 * scale + 1e-300) atomicOr(mismatch, 1);
 }
 
 // lumped mass by the vertex rule, M_A = rho * sum of vertex det J of the elements around A
@@ -243,13 +252,28 @@ __global__ void k_gather_A(Mesh M, const T* __restrict__ F, double tau, double t
   y[g] = w;
 }
 
-// exp(H) on one workgroup
+// rest-state element stiffness of a congruent mesh (one column per thread)
+__global__ void k_stiffness(Mesh M, double* Ke, float* Ke32) {
+  for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) Ke[i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x < 24) ke_column(M, threadIdx.x, Ke);
+  __syncthreads();
+  for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) Ke32[i] = float(Ke[i]);
+}
+
+void launch_stiffness(const Mesh& M, double* Ke, float* Ke32, hipStream_t st) {
+  k_stiffness<<<1, 64, 0, st>>>(M, Ke, Ke32);
+}
+
+// exp(H) on one workgroup; scratch (expm_scratch(m) doubles) in LDS when use_lds, else scr
 __global__ __launch_bounds__(kThreads) void k_expm(int m, const double* __restrict__ H, double* __restrict__ E,
-                                                   double* __restrict__ scr) {
+                                                   double* __restrict__ scr, int use_lds) {
+  extern __shared__ double dyn[];
   __shared__ double red[16];
   __shared__ int ired[16];
-  const double* R = wg_expm(H, m, m, scr, red, ired);
-  for (int i = threadIdx.x; i < m * m; i += blockDim.x) E[i] = R[i];
+  const double* R = use_lds ? wg_expm(H, m, m, dyn, red, ired) : wg_expm_global(H, m, m, scr, red, ired);
+  const int ld = expm_ld(m);
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) E[i] = R[(size_t)(i / m) * ld + (i % m)];
 }
 
 // ---------------------------------------------------------------------------------------
@@ -363,60 +387,110 @@ __global__ __launch_bounds__(256) void k_energy_final(Mesh M, double t, const do
 // ---------------------------------------------------------------------------------------
 // persistent projection kernel: one cooperative launch per exp(tau A) w
 // ---------------------------------------------------------------------------------------
-template <typename T, int MODEL>
+// LDS: red[32] | yb[kMaxM] | ke[24 kKeLd] | (compact WY: T[m_max^2] | vals[2 m_max] | gp[kThreads]) |
+//      ints: flag[16], ired[16] | union of the slice buffers lw, lv (2 chunk)
+//      and the check point's expm scratch (ex_cap doubles)
+static size_t expv_head_doubles(int ortho, int m_max) {
+  size_t d = 32 + kMaxM + 24 * kKeLd + 16;
+  if (ortho == 1) d += (size_t)m_max * m_max + 2 * (size_t)m_max + kThreads;
+  return d;
+}
+
+template <typename T, int MODEL, int ORTHO>
 __global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
   extern __shared__ double lds[];
   const int C = A.W.chunk;
-  double* lw = lds;
-  double* lv = lds + C;
-  double* red = lv + C;
+  const int mm = A.cfg.m_max;
+  double* red = lds;
   double* yb = red + 32;
-  int* flag = (int*)(yb + kMaxM);
+  double* ke = yb + kMaxM;
+  double* p = ke + 24 * kKeLd;
+  KLds X{nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+  if (MODEL == kLinear && A.M.ke != nullptr) {
+    T* k = (T*)ke;
+    for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x)
+      k[i] = (sizeof(T) == 8) ? T(A.M.ke[i]) : T(A.M.ke32[i]);
+    X.ke = ke;
+  }
+  if (ORTHO == 1) {
+    X.T = p;
+    X.vals = X.T + mm * mm;
+    X.gp = X.vals + 2 * mm;
+    p = X.gp + kThreads;
+  }
+  int* ints = (int*)p;
+  int* flag = ints;
+  X.ired = ints + 16;
+  double* U = p + 16;
+  double* lw = U;
+  double* lv = U + C;
+  X.ex = U;
+  X.ex_cap = A.W.ex_cap;
   if (threadIdx.x == 0) *flag = 1;   // workgroup alive flag (cleared on a synchronisation timeout)
   __syncthreads();
-  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false, 0u};
-  expv_body<T, MODEL>(tm, A, lw, lv, red, yb, flag);
+  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false, 0u,
+              A.W.vring, A.W.vw, 0u};
+  expv_body<T, MODEL, GridTeam, ORTHO>(tm, A, lw, lv, red, yb, flag, X);
 }
 
-size_t expv_lds_bytes(int chunk) { return (size_t)(2 * chunk + 32 + kMaxM) * sizeof(double) + 16 * sizeof(int); }
+constexpr size_t kLdsLimit = 160 * 1024;
+
+size_t expv_lds_head_bytes(int ortho, int m_max) { return expv_head_doubles(ortho, m_max) * sizeof(double); }
+
+size_t expv_lds_bytes(int chunk, int ortho, int m_max) {
+  const size_t head = expv_lds_head_bytes(ortho, m_max);
+  const size_t room = kLdsLimit > head ? kLdsLimit - head : 0;
+  const size_t want = (size_t)expm_scratch(m_max) * sizeof(double);
+  size_t u = 2 * (size_t)chunk * sizeof(double);
+  const size_t ex = want < room ? want : room;
+  if (u < ex) u = ex;
+  return head + u;
+}
 
 template <typename T, int MODEL>
-static const void* expv_fn() {
-  return reinterpret_cast<const void*>(&k_expv<T, MODEL>);
+static const void* expv_fn(int ortho) {
+  return ortho == 1 ? reinterpret_cast<const void*>(&k_expv<T, MODEL, 1>)
+                    : reinterpret_cast<const void*>(&k_expv<T, MODEL, 0>);
 }
 
-static const void* expv_kernel(int prec, int model) {
+static const void* expv_kernel(int prec, int model, int ortho) {
   if (prec == 0) {
-    if (model == kLinear) return expv_fn<double, kLinear>();
-    if (model == kNH) return expv_fn<double, kNH>();
-    return expv_fn<double, kYeoh>();
+    if (model == kLinear) return expv_fn<double, kLinear>(ortho);
+    if (model == kNH) return expv_fn<double, kNH>(ortho);
+    return expv_fn<double, kYeoh>(ortho);
   }
-  if (model == kLinear) return expv_fn<float, kLinear>();
-  if (model == kNH) return expv_fn<float, kNH>();
-  return expv_fn<float, kYeoh>();
+  if (model == kLinear) return expv_fn<float, kLinear>(ortho);
+  if (model == kNH) return expv_fn<float, kNH>(ortho);
+  return expv_fn<float, kYeoh>(ortho);
 }
 
-hipError_t expv_max_blocks(int prec, int model, int chunk, int* blocks_per_cu) {
-  const void* fn = expv_kernel(prec, model);
-  const size_t lds = expv_lds_bytes(chunk);
+hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int* blocks_per_cu) {
+  const void* fn = expv_kernel(cfg.prec, model, cfg.ortho);
+  const size_t lds = expv_lds_bytes(chunk, cfg.ortho, cfg.m_max);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds);
 }
 
-// empty all-reduce ring and zero barrier flags of a team before a launch
-__global__ void k_prep_team(unsigned long long* flags, unsigned long long* ring, int G) {
-  for (int i = threadIdx.x; i < G; i += blockDim.x) flags[i] = 0ull;
-  for (int i = threadIdx.x; i < kRing * G; i += blockDim.x) ring[i] = kEmpty;
+// empty all-reduce rings and zero barrier flags of a team before a launch
+__global__ void k_prep_team(unsigned long long* flags, unsigned long long* ring, unsigned long long* vring, int G,
+                            int nv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < G) flags[i] = 0ull;
+  if (i < kRing * G) ring[i] = kEmpty;
+  if (i < nv) vring[i] = kEmpty;
 }
 
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
-  k_prep_team<<<1, 256, 0, st>>>(a.W.flags, a.W.ring, a.W.G);
-  const void* fn = expv_kernel(prec, a.M.model);
-  const size_t lds = expv_lds_bytes(a.W.chunk);
+  const int nv = a.cfg.ortho == 1 ? kRing * a.W.G * a.W.vw : 0;
+  const int n = nv > kRing * a.W.G ? nv : kRing * a.W.G;
+  k_prep_team<<<(n + 255) / 256, 256, 0, st>>>(a.W.flags, a.W.ring, a.W.vring, a.W.G, nv);
+  const void* fn = expv_kernel(prec, a.M.model, a.cfg.ortho);
+  const size_t lds = expv_lds_bytes(a.W.chunk, a.cfg.ortho, a.cfg.m_max);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ExpvArgs copy = a;
+  copy.W.ex_cap = (int)((lds - expv_lds_head_bytes(a.cfg.ortho, a.cfg.m_max)) / sizeof(double));
   void* args[] = {&copy};
   return hipLaunchCooperativeKernel(fn, dim3(a.W.G), dim3(kThreads), args, (unsigned)lds, st);
 }
@@ -484,7 +558,15 @@ void launch_apply_A(const Mesh& M, const OpArgs& op, int prec, const double* x, 
 }
 
 void launch_expm(int m, const double* H, double* E, double* scr, hipStream_t st) {
-  k_expm<<<1, kThreads, 0, st>>>(m, H, E, scr);
+  const size_t lds = (size_t)expm_scratch(m) * sizeof(double);
+  if (lds <= 150 * 1024) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_expm), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) == hipSuccess) {
+      k_expm<<<1, kThreads, lds, st>>>(m, H, E, scr, 1);
+      return;
+    }
+  }
+  k_expm<<<1, kThreads, 0, st>>>(m, H, E, scr, 0);
 }
 
 int energy_blocks(const Mesh& M) { return nblk(M.n_elems, 256); }

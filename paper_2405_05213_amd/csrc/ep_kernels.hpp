@@ -5,8 +5,10 @@
 
 namespace ep {
 
-size_t expv_lds_bytes(int chunk);
-hipError_t expv_max_blocks(int prec, int model, int chunk, int* blocks_per_cu);
+size_t expv_lds_bytes(int chunk, int ortho, int m_max);
+size_t expv_lds_head_bytes(int ortho, int m_max);
+void launch_stiffness(const Mesh& M, double* Ke, float* Ke32, hipStream_t st);
+hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int* blocks_per_cu);
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
 
 void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,

@@ -2,9 +2,14 @@
 // (Sec. 4.3 of the paper), executed by a team of workgroups inside one launch:
 //   * operator apply (Sec. 2.3): element forces of the u-part (matrix-free hex8, fused
 //     M^{-1/2} scaling), then a per-DOF gather over the node's element slots;
-//   * Arnoldi with modified Gram-Schmidt: each projection h_ij = <w, v_i> is taken on the
-//     vector already reduced by the previous ones; the team's slice of w stays in LDS and
-//     every projection costs one team all-reduce;
+//   * Arnoldi with modified Gram-Schmidt, in one of two forms:
+//     - sequential: each projection h_ij = <w, v_i> is taken on the vector already reduced
+//       by the previous ones; the team's slice of w stays in LDS and every projection costs
+//       one team all-reduce (j + 1 reductions in step j);
+//     - compact WY: the same recurrence written as (I + L_j) h = V_j^T w, with L_j the
+//       strictly lower triangle of V_j^T V_j; V_j^T w and the new row of L_j form one
+//       vector all-reduce, T_j = (I + L_j)^{-1} grows by one row per step and h = T_j V_j^T w
+//       (2 reductions per step, norm included);
 //   * at check points workgroup 0 exponentiates H_j and evaluates the error estimate
 //     eps_j = h_{j+1,j} ||w|| |[exp(H_j)]_{j,1}|; the decision is broadcast;
 //   * the result ||w|| V_m exp(H_m) e_1 is combined in place;
@@ -20,6 +25,7 @@ constexpr double kBreakdown = 1e-14;
 
 // One workgroup acting alone (batched instances): team barrier = workgroup barrier.
 struct BlockTeam {
+  static constexpr bool kVecReduce = false;
   int G = 1, rank = 0;
   bool dead = false;
   __device__ bool sync(int*) {
@@ -29,6 +35,20 @@ struct BlockTeam {
   __device__ double allreduce(double p, double* red, int*, bool = false) { return block_sum(p, red); }
   __device__ double post(double p, double* red, int*, bool) { return block_sum(p, red); }
   __device__ double wait(double p, int*, bool, double* = nullptr) { return p; }
+};
+
+// LDS scratch of a projection: T (m_max x m_max, row major), the step's inner products
+// (2 m_max) and reduction partials (blockDim.x) of the compact-WY form; the region ex of
+// ex_cap doubles that the check point may use for exp(H_j) (it overlays the slice buffers,
+// which the check does not need); integer scratch of the pivoting solve.
+struct KLds {
+  double* ke;                 // rest-state element stiffness (T-typed, 24 x kKeLd) or null
+  double* T;
+  double* vals;
+  double* gp;
+  double* ex;
+  int ex_cap;
+  int* ired;
 };
 
 // Entries of the next basis vector's slice that a thread can hold in registers while a
@@ -58,12 +78,16 @@ __device__ __forceinline__ int read_err(const int* err) {
   return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Element forces of this team member's elements (operator apply, part 1).
+// Element forces of this team member's elements (operator apply, part 1).  With the
+// element stiffness of a congruent mesh in LDS (ke) the linear-elastic operator is K_e x_e.
 template <typename T, int MODEL>
 __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, const double* src,
-                                                         double hinv, T* F, int rank, int G) {
+                                                         double hinv, T* F, int rank, int G, const T* ke) {
   bool okA = true;
-  if (elem_lanes<T, MODEL>() == 8) {
+  if (MODEL == kLinear && ke != nullptr) {
+    for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
+      elem_force_ke<T>(M, e, src, hinv, ke, F);
+  } else if (elem_lanes<T, MODEL>() == 8) {
     // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
     for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
       okA &= elem_force_qp<T, MODEL>(M, op, e, src, hinv, true, F);
@@ -77,10 +101,72 @@ __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, 
   return okA;
 }
 
+// Check point of step j (shared by both orthogonalisation forms): workgroup 0 exponentiates
+// H_j and decides; on convergence X <- V_j y with y = beta exp(H_j) e_1.  Returns 0 to go
+// on, 1 when the projection ends (R filled), -1 when the team died.
+template <class Team>
+__device__ __forceinline__ int check_point(Team& tm, const ExpvArgs& A, int j, double hn, double beta,
+                                           bool breakdown, double* red, double* yb, const KLds& X, int* flag,
+                                           int nloc, int c0, ProjResult& R) {
+  const KWork& W = A.W;
+  const KrylovCfg& cfg = A.cfg;
+  const int ldH = cfg.m_max;
+  const size_t Lp = (size_t)A.M.Lp;
+  if (tm.rank == 0) {
+    __syncthreads();
+    // two instantiations, so that the LDS one addresses its scratch as LDS
+    const double* E = (X.ex != nullptr && expm_scratch(j) <= X.ex_cap) ? wg_expm(W.H, ldH, j, X.ex, red, X.ired)
+                                                                       : wg_expm_global(W.H, ldH, j, W.Escr, red, X.ired);
+    const int le = expm_ld(j);
+    const double eps = hn * beta * fabs(E[(size_t)(j - 1) * le]);
+    int dec = 0;
+    if (breakdown || cfg.m_fixed > 0 || eps <= cfg.tol * beta) dec = 1;
+    else if (j == cfg.m_max) dec = 2;
+    for (int t = threadIdx.x; t < j; t += blockDim.x) W.y[t] = beta * E[(size_t)t * le];
+    if (threadIdx.x == 0) {
+      W.ctrl->decision = dec;
+      W.ctrl->bcast[0] = eps;
+    }
+  }
+  if (!tm.sync(flag)) return -1;
+  const int dec = __hip_atomic_load(&W.ctrl->decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double eps = W.ctrl->bcast[0];
+  R.m = j;
+  R.eps = eps;
+  R.breakdown = breakdown;
+  if (dec == 2) { R.converged = false; return 1; }
+  if (dec == 1) {
+    for (int t = threadIdx.x; t < j; t += blockDim.x) yb[t] = W.y[t];
+    __syncthreads();
+    double part = 0.0;
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
+      const double* Vi = W.V + c0 + i;
+      double s = 0.0;
+      int t = 0;
+      for (; t + 8 <= j; t += 8) {
+        double q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = Vi[(size_t)(t + u) * Lp];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += yb[t + u] * q[u];
+      }
+      for (; t < j; ++t) s += yb[t] * Vi[(size_t)t * Lp];
+      W.X[c0 + i] = s;
+      part += s * s;
+    }
+    R.beta_next = sqrt(tm.allreduce(part, red, flag, true));
+    R.converged = true;
+    return 1;
+  }
+  // not converged yet: workgroup 0 can only rewrite the broadcast after the next operator
+  // barrier, which every workgroup reaches after reading it
+  return 0;
+}
+
 // X <- exp(f A) X on entry ||X|| = beta.  Every workgroup returns the same result.
 template <typename T, int MODEL, class Team>
 __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
-                              double* lw, double* lv, double* red, double* yb, int* flag) {
+                              double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
   const KWork& W = A.W;
   const KrylovCfg& cfg = A.cfg;
@@ -104,7 +190,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
   for (int j = 1; j <= mcap; ++j) {
     // ---- operator apply, part 1: element forces of the u-part of v_{j-1}
-    const bool okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G);
+    const bool okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;
     {
@@ -204,42 +290,197 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     if (cfg.m_fixed > 0) check = breakdown || j == cfg.m_fixed;
     else check = breakdown || j == cfg.m_max || (j % cfg.check_every == 0 && j >= hint - cfg.check_every);
     if (check) {
-      if (lead) {
-        __syncthreads();
-        const double* E = wg_expm(W.H, ldH, j, W.Escr, red, flag);
-        const double eps = hn * beta * fabs(E[(size_t)(j - 1) * j]);
-        int dec = 0;
-        if (breakdown || cfg.m_fixed > 0 || eps <= cfg.tol * beta) dec = 1;
-        else if (j == cfg.m_max) dec = 2;
-        for (int t = threadIdx.x; t < j; t += blockDim.x) W.y[t] = beta * E[(size_t)t * j];
-        if (threadIdx.x == 0) {
-          W.ctrl->decision = dec;
-          W.ctrl->bcast[0] = eps;
+      const int c = check_point(tm, A, j, hn, beta, breakdown, red, yb, X, flag, nloc, c0, R);
+      if (c != 0) return R;
+    }
+    src = W.Wun;
+  }
+  R.converged = false;
+  return R;
+}
+
+// Compact-WY form of the projection (see the file header).  Per step: the operator barrier,
+// one vector all-reduce of the 2j - 1 inner products, the fenced norm all-reduce.
+template <typename T, int MODEL, class Team>
+__device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
+                                  double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
+  const Mesh& M = A.M;
+  const KWork& W = A.W;
+  const KrylovCfg& cfg = A.cfg;
+  ProjResult R{0, 0.0, true, true, 0, 0.0, 0};
+  if (beta == 0.0) return R;
+  if (!(beta < INFINITY)) { R.status = kErrNonfinite; return R; }
+  const int C = W.chunk;
+  const int c0 = tm.rank * C;
+  const int nloc = max(0, min(c0 + C, M.Lp) - c0);
+  const int n3 = M.n3;
+  const size_t Lp = (size_t)M.Lp;
+  const int ldH = cfg.m_max, ldT = cfg.m_max;
+  const int mcap = cfg.m_fixed > 0 ? cfg.m_fixed : cfg.m_max;
+  const bool lead = tm.rank == 0;
+  const int nw = (int)(blockDim.x >> 6), lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T* F = (sizeof(T) == 8) ? (T*)W.F : (T*)W.F32;
+
+  double hinv = 1.0 / beta;
+  const double* src = W.X;
+  for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
+    const double v = W.X[c0 + i] * hinv;
+    W.V[c0 + i] = v;
+    lv[i] = v;                                   // lv: slice of the newest basis vector
+  }
+  double hmax = 0.0;
+
+  for (int j = 1; j <= mcap; ++j) {
+    const bool okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
+    if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
+    if (!tm.sync(flag)) return R;
+    {
+      const int er = read_err(&W.ctrl->err);
+      if (er != 0) { R.status = er; return R; }
+    }
+    R.nmv += 1;
+    // w = f A v_{j-1} on the own slice
+    const double xs = src[2 * n3] * hinv * M.s_inv;
+    for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
+      const int g = c0 + i;
+      double w;
+      if (g < n3) {
+        w = f * (src[n3 + g] * hinv);
+      } else if (g < 2 * n3) {
+        const int d = g - n3;
+        const double s = gather_force(M, F, d / 3, d - (d / 3) * 3);
+        w = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
+      } else {
+        w = 0.0;
+      }
+      lw[i] = w;
+    }
+    __syncthreads();
+    // partial inner products b_k = <v_k, w> (k < j) and l_k = <v_k, v_{j-1}> (k < j - 1):
+    // each wave takes one (value, segment) unit at a time, lanes stride the segment
+    const int S = max(1, nw / j);
+    const int seg = (nloc + S - 1) / S;
+    const int K2 = 2 * j;
+    for (int u = wv; u < j * S; u += nw) {
+      const int k = u % j, sg = u / j;
+      const int t0 = sg * seg, t1 = min(nloc, t0 + seg);
+      double b = 0.0, l = 0.0;
+      if (k == j - 1) {
+        for (int t = t0 + lane; t < t1; t += 64) b += lv[t] * lw[t];
+      } else {
+        // 8 loads in flight per lane
+        const double* Vk = W.V + (size_t)k * Lp + c0;
+        for (int tb = t0 + lane; tb < t1; tb += 64 * 8) {
+          double q[8];
+#pragma unroll
+          for (int r = 0; r < 8; ++r) q[r] = tb + 64 * r < t1 ? Vk[tb + 64 * r] : 0.0;
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const int t = tb + 64 * r;
+            if (t < t1) {
+              b += q[r] * lw[t];
+              l += q[r] * lv[t];
+            }
+          }
         }
       }
-      if (!tm.sync(flag)) return R;
-      const int dec = __hip_atomic_load(&W.ctrl->decision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const double eps = W.ctrl->bcast[0];
-      R.m = j;
-      R.eps = eps;
-      R.breakdown = breakdown;
-      if (dec == 2) { R.converged = false; return R; }
-      if (dec == 1) {
-        for (int t = threadIdx.x; t < j; t += blockDim.x) yb[t] = W.y[t];
-        __syncthreads();
-        part = 0.0;
-        for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
-          double s = 0.0;
-          for (int t = 0; t < j; ++t) s += yb[t] * W.V[(size_t)t * Lp + c0 + i];
-          W.X[c0 + i] = s;
-          part += s * s;
-        }
-        R.beta_next = sqrt(tm.allreduce(part, red, flag, true));
-        R.converged = true;
-        return R;
+      b = wave_sum(b);
+      l = wave_sum(l);
+      if (lane == 0) {
+        X.gp[sg * K2 + k] = b;
+        X.gp[sg * K2 + j + k] = l;
       }
-      // not converged yet: workgroup 0 can only rewrite the broadcast after the next
-      // operator barrier, which every workgroup reaches after reading it
+    }
+    __syncthreads();
+    const int K = 2 * j - 1;
+    for (int t = threadIdx.x; t < K; t += blockDim.x) {
+      double s = 0.0;
+      for (int sg = 0; sg < S; ++sg) s += X.gp[sg * K2 + t];
+      X.vals[t] = s;
+    }
+    __syncthreads();
+    if (!tm.allreduce_vec(X.vals, K, X.gp, flag)) return R;
+    // new row of T = (I + L)^{-1}: T[j-1][i] = -sum_{k=i}^{j-2} l_k T[k][i]; then h = T b.
+    // Eight lanes per row, each summing every eighth term, then a 3-step butterfly.
+    const double* bv = X.vals;
+    const double* lv2 = X.vals + j;
+    double* Tr = X.T + (size_t)(j - 1) * ldT;
+    const int sub = threadIdx.x & 7;
+    for (int i = threadIdx.x >> 3; i < j - 1; i += blockDim.x >> 3) {
+      double s = 0.0;
+      for (int k = i + sub; k < j - 1; k += 8) s += lv2[k] * X.T[(size_t)k * ldT + i];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      if (sub == 0) Tr[i] = -s;
+    }
+    if (threadIdx.x == 0) Tr[j - 1] = 1.0;
+    __syncthreads();
+    for (int i = threadIdx.x >> 3; i < j; i += blockDim.x >> 3) {
+      const double* Ti = X.T + (size_t)i * ldT;
+      double s = 0.0;
+      for (int k = sub; k <= i; k += 8) s += Ti[k] * bv[k];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      if (sub == 0) {
+        yb[i] = s;
+        if (lead) W.H[(size_t)i * ldH + (j - 1)] = s;
+      }
+    }
+    __syncthreads();
+    bool finite = true;
+    for (int i = 0; i < j; ++i) {
+      const double h = yb[i];
+      hmax = fmax(hmax, fabs(h));
+      finite &= fabs(h) < INFINITY;
+    }
+    // w <- w - V_j h, its norm, and the unnormalised vector for the next operator apply
+    double part = 0.0;
+    for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+      double w = lw[t];
+      const double* Vt = W.V + c0 + t;
+      int k = 0;
+      for (; k + 8 <= j - 1; k += 8) {
+        double q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = Vt[(size_t)(k + u) * Lp];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) w -= yb[k + u] * q[u];
+      }
+      for (; k < j - 1; ++k) w -= yb[k] * Vt[(size_t)k * Lp];
+      w -= yb[j - 1] * lv[t];
+      lw[t] = w;
+      W.Wun[c0 + t] = w;
+      part += w * w;
+    }
+    const double hn = sqrt(tm.allreduce(part, red, flag, true));
+    if (tm.dead) return R;
+    if (lead && threadIdx.x == 0) W.H[(size_t)j * ldH + (j - 1)] = hn;
+    hmax = fmax(hmax, hn);
+    finite &= hn < INFINITY;
+    if (!finite) { R.status = kErrNonfinite; return R; }
+    const bool breakdown = hn <= kBreakdown * hmax;
+    if (!breakdown) {
+      hinv = 1.0 / hn;
+      double* Vj = W.V + (size_t)j * Lp + c0;
+      for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+        const double v = lw[t] * hinv;
+        Vj[t] = v;
+        lv[t] = v;
+      }
+    }
+    bool check;
+    if (cfg.m_fixed > 0) check = breakdown || j == cfg.m_fixed;
+    else check = breakdown || j == cfg.m_max || (j % cfg.check_every == 0 && j >= hint - cfg.check_every);
+    if (check) {
+      const int c = check_point(tm, A, j, hn, beta, breakdown, red, yb, X, flag, nloc, c0, R);
+      if (c != 0) return R;
+      if (lead && X.ex != nullptr && expm_scratch(j) <= X.ex_cap) {
+        // exp(H_j) overwrote the slice buffers of workgroup 0: reload v_j (w is rebuilt)
+        const double* Vj = W.V + (size_t)j * Lp + c0;
+        for (int t = threadIdx.x; t < nloc; t += blockDim.x) lv[t] = Vj[t];
+      }
     }
     src = W.Wun;
   }
@@ -249,9 +490,9 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
 // wbar_out = exp(tau A) wbar_in with the sticky substep count and subspace-size hint of
 // this projection kind; writes statistics and sticky errors.
-template <typename T, int MODEL, class Team>
+template <typename T, int MODEL, class Team, int ORTHO = 0>
 __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, double* red, double* yb,
-                          int* flag) {
+                          int* flag, const KLds& cx) {
   const Mesh& M = A.M;
   const KWork& W = A.W;
   const KrylovCfg& cfg = A.cfg;
@@ -277,7 +518,11 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
     bool ok = true;
     int hint_run = hint;
     for (int sub = 0; sub < k; ++sub) {
-      ProjResult r = project<T, MODEL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag);
+      ProjResult r;
+      if constexpr (Team::kVecReduce && ORTHO == 1)
+        r = project_cwy<T, MODEL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+      else
+        r = project<T, MODEL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       if (tm.dead) return;
       nmv += r.nmv;
       if (r.status != 0) { status = r.status; ok = false; break; }

@@ -43,6 +43,9 @@ _SIGS = {
     "ep_set_traction": [_vp, _i64, _vp, _vp, _i64, _vp, _vp],
     "ep_set_krylov": [_vp, _dbl, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dbl],
     "ep_set_precision": [_vp, C.c_int],
+    "ep_set_orthogonalization": [_vp, C.c_int],
+    "ep_get_launch": [_vp, _P(C.c_int), _P(C.c_int), _P(C.c_int)],
+    "ep_get_orthogonalization": [_vp, _P(C.c_int)],
     "ep_set_launch": [_vp, C.c_int],
     "ep_autotune": [_vp, _dbl, C.c_int, C.c_int, _P(C.c_int), _P(_dbl)],
     "ep_workspace_size": [_vp, _P(C.c_size_t)],
@@ -77,6 +80,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2405_05213_amd.build")
+        # torch's HIP runtime must be initialised first: loading the library's device code
+        # before it leaves torch without visible GPUs
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)
@@ -157,6 +163,21 @@ class Context:
 
     def set_precision(self, prec: str):
         self._call("ep_set_precision", PRECISIONS[prec])
+
+    def set_orthogonalization(self, mode: int):
+        """-1 automatic, 0 sequential MGS, 1 MGS in compact-WY form (see include/ep.h)."""
+        self._call("ep_set_orthogonalization", int(mode))
+
+    def orthogonalization(self) -> int:
+        m = C.c_int()
+        self._call("ep_get_orthogonalization", C.byref(m))
+        return m.value
+
+    def launch(self):
+        """(workgroups, entries per workgroup, congruent mesh) of the persistent kernel."""
+        g, ch, cg = C.c_int(), C.c_int(), C.c_int()
+        self._call("ep_get_launch", C.byref(g), C.byref(ch), C.byref(cg))
+        return g.value, ch.value, bool(cg.value)
 
     def set_launch(self, workgroups: int):
         self._call("ep_set_launch", int(workgroups))
@@ -308,7 +329,7 @@ def batch_from_problems(probs, device=0, tol=None, m_max=32, check_every=4, m_fi
 
 
 def solver_from_problem(prob, device=0, tol=None, m_max=64, check_every=4, m_fixed=0, k_fixed=0,
-                        max_substeps=64, s0=-1.0, precision="f64", workgroups=0, stream=None):
+                        max_substeps=64, s0=-1.0, precision="f64", workgroups=0, stream=None, ortho=-1):
     """Context set up from a workloads.Problem, bound and at the problem's initial state."""
     ctx = Context(device, stream=stream)
     ctx.set_mesh(prob.xyz, prob.conn)
@@ -320,6 +341,7 @@ def solver_from_problem(prob, device=0, tol=None, m_max=64, check_every=4, m_fix
     ctx.set_krylov(prob.tol if tol is None else tol, m_max, check_every, m_fixed, k_fixed, max_substeps, s0)
     ctx.set_precision(precision)
     ctx.set_launch(workgroups)
+    ctx.set_orthogonalization(ortho)
     ctx.bind()
     ctx.set_state(0.0, prob.u0, prob.v0)
     return ctx

@@ -87,3 +87,31 @@ def test_host_context_cannot_bind():
     assert rc == epmod.EP_ERR_HIP
     rc = L.ep_bind_workspace(c.h, C.c_void_p(257), n)
     assert rc == epmod.EP_ERR_WORKSPACE
+
+
+def test_orthogonalization_modes():
+    """Compact-WY MGS is the default up to m_max = 64; larger subspaces use the sequential
+    form; an explicit compact-WY request beyond 64 is refused."""
+    p = config("c1")
+
+    def ctx(m_max, mode=None):
+        c = _host_ctx()
+        c.set_mesh(p.xyz, p.conn)
+        c.set_material("linear", (200e9, 0.3), 7800.0)
+        c.set_krylov(m_max=m_max)
+        if mode is not None:
+            c.set_orthogonalization(mode)
+        return c
+
+    assert ctx(64).orthogonalization() == 1
+    assert ctx(65).orthogonalization() == 0
+    assert ctx(64, 0).orthogonalization() == 0
+    c = ctx(128, 1)
+    with pytest.raises(epmod.EPError) as e:
+        c.workspace_size()
+    assert e.value.code == epmod.EP_ERR_ARG
+    with pytest.raises(epmod.EPError) as e:
+        _host_ctx().set_orthogonalization(2)
+    assert e.value.code == epmod.EP_ERR_ARG
+    # the vector all-reduce slots make the compact-WY workspace larger
+    assert ctx(64, 1).workspace_size() >= ctx(64, 0).workspace_size()

@@ -62,12 +62,16 @@ def test_expm_matches_oracle(m, scale):
     assert np.abs(E - R).max() <= 1e-13 * max(1.0, np.abs(R).max()) * max(1.0, scale / 10)
 
 
-@pytest.mark.parametrize("name,over,workgroups", [("c1", {}, 1), ("c1", {}, 4), ("c2", dict(nx=20, ny=4, nz=4), 0)])
-def test_arnoldi_matches_oracle(name, over, workgroups):
-    """Arnoldi-MGS: same Hessenberg matrix and basis as the oracle on the same operator."""
-    say(f"[arnoldi] {name} {over} G={workgroups}")
+@pytest.mark.parametrize("ortho", [0, 1])
+@pytest.mark.parametrize("name,over,workgroups", [("c1", {}, 1), ("c1", {}, 4), ("c2", dict(nx=20, ny=4, nz=4), 0),
+                                                  ("c2", dict(nx=20, ny=4, nz=4), 37)])
+def test_arnoldi_matches_oracle(name, over, workgroups, ortho):
+    """Arnoldi-MGS (sequential and compact-WY forms): same Hessenberg matrix and basis as the
+    oracle on the same operator."""
+    say(f"[arnoldi] {name} {over} G={workgroups} ortho={ortho}")
     p = config(name, **over)
-    ctx, orc = pair(p, m_max=40, workgroups=workgroups)
+    ctx, orc = pair(p, m_max=40, workgroups=workgroups, ortho=ortho)
+    assert ctx.orthogonalization() == ortho
     rng = np.random.default_rng(7)
     N = orc.N
     w = np.concatenate([orc.Mh * rng.normal(0, 1e-5, N), orc.Mh * rng.normal(0, 1e-2, N), [1.0]])
@@ -88,11 +92,12 @@ def test_arnoldi_matches_oracle(name, over, workgroups):
         assert rel(from_gpu_vec(orc, Vg[j]), Vo[j]) < 1e-8
 
 
+@pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("dt,workgroups", [(2e-5, 1), (1e-4, 2), (4e-4, 3)])
-def test_expv_matches_oracle(dt, workgroups):
-    say(f"[expv] c1 dt={dt} G={workgroups}")
+def test_expv_matches_oracle(dt, workgroups, ortho):
+    say(f"[expv] c1 dt={dt} G={workgroups} ortho={ortho}")
     p = config("c1")
-    ctx, orc = pair(p, m_max=48, workgroups=workgroups)
+    ctx, orc = pair(p, m_max=48, workgroups=workgroups, ortho=ortho)
     rng = np.random.default_rng(11)
     N = orc.N
     w = np.concatenate([orc.Mh * rng.normal(0, 1e-5, N), orc.Mh * rng.normal(0, 1e-2, N), [1.0]])
@@ -105,12 +110,14 @@ def test_expv_matches_oracle(dt, workgroups):
     assert rel(from_gpu_vec(orc, _np(y)), yo) < 1e-9
 
 
+@pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("mode", ["fixed", "adaptive"])
-def test_linear_steps_c1(mode):
+def test_linear_steps_c1(mode, ortho):
     """200 steps of the 10x2x2 linear cantilever (dt 1e-4, tol 1e-10) against the oracle."""
-    say(f"[steps] c1 linear {mode}")
+    say(f"[steps] c1 linear {mode} ortho={ortho}")
     p = config("c1")
     kw = dict(m_max=64) if mode == "adaptive" else dict(m_max=64, m_fixed=32, k_fixed=1)
+    kw["ortho"] = ortho
     ctx, orc = pair(p, **kw)
     ctx.step(p.dt, p.n_steps)
     t, u, v = ctx.get_state()
@@ -131,12 +138,14 @@ def test_linear_steps_c1(mode):
 @pytest.mark.parametrize("model,name,over", [("nh", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4)),
                                               ("yeoh", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3))])
 @pytest.mark.parametrize("mode", ["fixed", "adaptive"])
-def test_nonlinear_steps(model, name, over, mode):
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_nonlinear_steps(model, name, over, mode, ortho):
     """Predictor-corrector steps of the Neo-Hookean / Yeoh solids against the oracle."""
-    say(f"[steps] {model} {name} {over} {mode}")
+    say(f"[steps] {model} {name} {over} {mode} ortho={ortho}")
     p = config(name, **over)
     n = 12
     kw = dict(m_max=48) if mode == "adaptive" else dict(m_max=48, m_fixed=24, k_fixed=1)
+    kw["ortho"] = ortho
     ctx, orc = pair(p, **kw)
     ctx.step(p.dt, n)
     t, u, v = ctx.get_state()
@@ -146,3 +155,17 @@ def test_nonlinear_steps(model, name, over, mode):
     ke, se, we = ctx.energy()
     ko, so_, wo = orc.energies()
     assert abs(se - so_) <= 1e-8 * (ko + so_ + abs(wo))
+
+
+@pytest.mark.parametrize("name,over,distorted,expect", [("c1", {}, False, True), ("c2", dict(nx=20, ny=4, nz=4), False, True),
+                                                        ("c1", {}, True, False)])
+def test_congruence_detection(name, over, distorted, expect):
+    """Box meshes with coordinates i*h (rounding noise in J) are congruent; distorted are not."""
+    say(f"[congruence] {name} {over} distorted={distorted}")
+    p = config(name, **over)
+    if distorted:
+        p = distort(p, 0.2, seed=5)
+    ctx, _ = pair(p)
+    g, chunk, cong = ctx.launch()
+    assert cong == expect
+    assert g >= 1 and chunk >= 64 and g * chunk >= 2 * 3 * p.n_nodes + 1
