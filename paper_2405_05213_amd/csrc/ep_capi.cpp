@@ -256,7 +256,7 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_eout = L.take(8 * 4);
   I.o_flags = L.take(4 * 4);
   I.o_wscr = L.take(c->batch ? 8 * 2 * Lp : 8);
-  I.o_ke = L.take(12 * 24 * kKeLd);
+  I.o_ke = L.take(8 * 24 * kKeLd);
 }
 
 static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
@@ -372,12 +372,10 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   M.s0 = auto_s0(c, I);
   M.s_inv = M.s0 != 0.0 ? 1.0 / M.s0 : 0.0;
   M.ke = nullptr;
-  M.ke32 = nullptr;
   if (M.congruent && I.n_elems > 0) {
-    launch_stiffness(M, dptr<double>(c, I.o_ke), reinterpret_cast<float*>(dptr<double>(c, I.o_ke) + 24 * kKeLd), st);
+    launch_stiffness(M, dptr<double>(c, I.o_ke), st);
     EP_HIP(c, hipGetLastError());
     M.ke = dptr<double>(c, I.o_ke);
-    M.ke32 = reinterpret_cast<const float*>(M.ke + 24 * kKeLd);
   }
   KWork& W = I.W;
   W.V = dptr<double>(c, I.o_V);

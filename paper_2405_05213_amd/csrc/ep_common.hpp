@@ -31,8 +31,8 @@ struct Mesh {
   const double* geo;          // per quadrature point: Jinv (3x3 row major) + w*detJ
   const float* geo32;
   int congruent;              // 1: one geometry set shared by all elements
-  const double* ke;           // congruent meshes: rest-state element stiffness (24 x kKeLd)
-  const float* ke32;          //   and its FP32 rounding; null otherwise
+  const double* ke;           // congruent meshes: rest-state element stiffness (24 x kKeLd),
+                              // null otherwise
   const double* mih;          // M^{-1/2} per DOF (0 on clamped DOFs)
   const double* mh;           // M^{1/2}  per DOF (0 on clamped DOFs)
   const double* p0bar;        // M^{-1/2} P0 per DOF (0 on clamped DOFs)

@@ -219,7 +219,12 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
   int nd[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+  // In FP32 the element's inputs are taken relative to node 0 (in FP64 before rounding):
+  // the forces depend on gradients only, and a large common translation would otherwise
+  // cost the deformation its significant bits.
+  constexpr bool shift = sizeof(T) == 4;
   T x[8][3];
+  double x0[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -227,22 +232,27 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
       const size_t d = (size_t)nd[a] * 3 + i;
       double v = src[d] * srcscale;
       if (scale_mih) v *= M.mih[d];
-      x[a][i] = T(v);
+      if (shift && a == 0) x0[i] = v;
+      x[a][i] = T(v - x0[i]);
       f[a][i] = T(0);
     }
   const int nsets = (MODEL == kLinear) ? 0 : op.nsets;
   T u0[8][3], u1[8][3];
   if (nsets >= 1) {
+    const double* ul = op.ulin[0];
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
-      for (int i = 0; i < 3; ++i) u0[a][i] = T(op.ulin[0][(size_t)nd[a] * 3 + i]);
+      for (int i = 0; i < 3; ++i)
+        u0[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
   }
   if (nsets >= 2) {
+    const double* ul = op.ulin[1];
 #pragma unroll
     for (int a = 0; a < 8; ++a)
 #pragma unroll
-      for (int i = 0; i < 3; ++i) u1[a][i] = T(op.ulin[1][(size_t)nd[a] * 3 + i]);
+      for (int i = 0; i < 3; ++i)
+        u1[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
   }
   double lam_d, mu_d;
   rest_lame(M.model, M.mp, lam_d, mu_d);
@@ -318,6 +328,7 @@ __device__ __forceinline__ void grad_gather(const QFactors<T>& Q, const int (&nd
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Dxi[i][j] = T(0);
+  double x0[3] = {0.0, 0.0, 0.0};     // FP32: inputs relative to node 0 (see elem_force)
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     const T d0 = Q.dN(a, 0), d1 = Q.dN(a, 1), d2 = Q.dN(a, 2);
@@ -326,7 +337,8 @@ __device__ __forceinline__ void grad_gather(const QFactors<T>& Q, const int (&nd
       const size_t d = (size_t)nd[a] * 3 + i;
       double xv = v[d] * sc;
       if (mih) xv *= mih[d];
-      const T x = T(xv);
+      if (sizeof(T) == 4 && a == 0) x0[i] = xv;
+      const T x = T(xv - x0[i]);
       Dxi[i][0] += x * d0;
       Dxi[i][1] += x * d1;
       Dxi[i][2] += x * d2;
@@ -470,30 +482,29 @@ __device__ __forceinline__ void ke_column(const Mesh& M, int c, double* Ke) {
     for (int i = 0; i < 3; ++i) Ke[(3 * a + i) * kKeLd + c] = f[a][i];
 }
 
-// Element forces F = K_e x_e of a congruent mesh with K_e in LDS: eight lanes per element,
-// lane a owns node a, loads its three inputs and obtains the other 21 by shuffles.
-// Every lane of the 8-lane group must call with the same e.
-template <typename T>
+// Element forces F = K_e x_e of a congruent mesh with K_e in LDS (FP64): eight lanes per
+// element, lane a owns node a, loads its three inputs and obtains the other 21 by
+// shuffles.  Every lane of the 8-lane group must call with the same e.
 __device__ __forceinline__ void elem_force_ke(const Mesh& M, int e, const double* src, double srcscale,
-                                              const T* Ke, T* F) {
+                                              const double* Ke, double* F) {
   const int lane = threadIdx.x & 63;
   const int a = lane & 7, base = lane & ~7;
   const int nd = M.conn[(size_t)e * 8 + a];
-  T xa[3];
+  double xa[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const size_t d = (size_t)nd * 3 + i;
-    xa[i] = T(src[d] * srcscale * M.mih[d]);
+    xa[i] = src[d] * srcscale * M.mih[d];
   }
-  T xe[24];
+  double xe[24];
 #pragma unroll
   for (int b = 0; b < 8; ++b)
 #pragma unroll
     for (int i = 0; i < 3; ++i) xe[3 * b + i] = __shfl(xa[i], base + b, 64);
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const T* row = Ke + (3 * a + i) * kKeLd;
-    T s = T(0);
+    const double* row = Ke + (3 * a + i) * kKeLd;
+    double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 24; ++c) s += row[c] * xe[c];
     F[((size_t)a * M.n_elems + e) * 3 + i] = s;

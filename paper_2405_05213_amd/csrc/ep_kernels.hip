@@ -253,17 +253,13 @@ __global__ void k_gather_A(Mesh M, const T* __restrict__ F, double tau, double t
 }
 
 // rest-state element stiffness of a congruent mesh (one column per thread)
-__global__ void k_stiffness(Mesh M, double* Ke, float* Ke32) {
+__global__ void k_stiffness(Mesh M, double* Ke) {
   for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) Ke[i] = 0.0;
   __syncthreads();
   if (threadIdx.x < 24) ke_column(M, threadIdx.x, Ke);
-  __syncthreads();
-  for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) Ke32[i] = float(Ke[i]);
 }
 
-void launch_stiffness(const Mesh& M, double* Ke, float* Ke32, hipStream_t st) {
-  k_stiffness<<<1, 64, 0, st>>>(M, Ke, Ke32);
-}
+void launch_stiffness(const Mesh& M, double* Ke, hipStream_t st) { k_stiffness<<<1, 64, 0, st>>>(M, Ke); }
 
 // exp(H) on one workgroup; scratch (expm_scratch(m) doubles) in LDS when use_lds, else scr
 __global__ __launch_bounds__(kThreads) void k_expm(int m, const double* __restrict__ H, double* __restrict__ E,
@@ -406,10 +402,8 @@ __global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
   double* ke = yb + kMaxM;
   double* p = ke + 24 * kKeLd;
   KLds X{nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
-  if (MODEL == kLinear && A.M.ke != nullptr) {
-    T* k = (T*)ke;
-    for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x)
-      k[i] = (sizeof(T) == 8) ? T(A.M.ke[i]) : T(A.M.ke32[i]);
+  if (MODEL == kLinear && sizeof(T) == 8 && A.M.ke != nullptr) {
+    for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) ke[i] = A.M.ke[i];
     X.ke = ke;
   }
   if (ORTHO == 1) {

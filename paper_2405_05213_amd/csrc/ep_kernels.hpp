@@ -7,7 +7,7 @@ namespace ep {
 
 size_t expv_lds_bytes(int chunk, int ortho, int m_max);
 size_t expv_lds_head_bytes(int ortho, int m_max);
-void launch_stiffness(const Mesh& M, double* Ke, float* Ke32, hipStream_t st);
+void launch_stiffness(const Mesh& M, double* Ke, hipStream_t st);
 hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int* blocks_per_cu);
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
 

@@ -79,15 +79,22 @@ __device__ __forceinline__ int read_err(const int* err) {
 }
 
 // Element forces of this team member's elements (operator apply, part 1).  With the
-// element stiffness of a congruent mesh in LDS (ke) the linear-elastic operator is K_e x_e.
+// element stiffness of a congruent mesh in LDS (ke) the FP64 linear-elastic operator is
+// K_e x_e.  The FP32 kernels keep the quadrature form: K_e rounded to FP32 no longer maps
+// rigid motions to zero force, and its rounding costs about four orders of magnitude of
+// energy accuracy on a bending cantilever.
 template <typename T, int MODEL>
 __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, const double* src,
                                                          double hinv, T* F, int rank, int G, const T* ke) {
   bool okA = true;
-  if (MODEL == kLinear && ke != nullptr) {
-    for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
-      elem_force_ke<T>(M, e, src, hinv, ke, F);
-  } else if (elem_lanes<T, MODEL>() == 8) {
+  if constexpr (MODEL == kLinear && sizeof(T) == 8) {
+    if (ke != nullptr) {
+      for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
+        elem_force_ke(M, e, src, hinv, (const double*)ke, (double*)F);
+      return true;
+    }
+  }
+  if (elem_lanes<T, MODEL>() == 8) {
     // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
     for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
       okA &= elem_force_qp<T, MODEL>(M, op, e, src, hinv, true, F);
