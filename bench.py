@@ -178,6 +178,55 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
     }
 
 
+def run_matvec(prob, u_lin, reps, stream, torch, args):
+    """Stand-alone operator apply y = H(u) x (FP64).  `reps` applies are captured in one
+    graph on a side stream (a single apply takes less time than a host-side launch), the
+    graph is replayed and timed with events; the replayed result is checked against the
+    eager one.  Algorithmic bytes of one apply: read x and write y (3 n_n doubles each),
+    read the connectivity (32 B per element), plus u (3 n_n doubles) for a secant material."""
+    from paper_2405_05213_amd import solver_from_problem
+    side = torch.cuda.Stream()
+    ctx = solver_from_problem(prob, m_max=4, stream=side.cuda_stream)
+    n3 = 3 * prob.n_nodes
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    x = torch.randn(n3, dtype=torch.float64, device="cuda", generator=gen)
+    y = torch.zeros_like(x)
+    u = None if u_lin is None else torch.as_tensor(u_lin, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ctx.apply_H(u, x, y)
+    y_eager = y.clone()
+    y.zero_()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        for _ in range(reps):
+            ctx.apply_H(u, x, y, sync=False)
+    graph.replay()
+    side.synchronize()
+    ok = bool(torch.equal(y, y_eager))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rounds = 5
+    with torch.cuda.stream(side):
+        e0.record(side)
+        for _ in range(rounds):
+            graph.replay()
+        e1.record(side)
+    side.synchronize()
+    ctx.sync()
+    us = e0.elapsed_time(e1) * 1e3 / (rounds * reps)
+    alg = (2 * n3 + (n3 if u is not None else 0)) * 8 + 32 * prob.n_elems
+    achieved = alg / (us * 1e-6) / 1e9
+    workgroups, chunk, congruent = ctx.launch()
+    path = ("node-by-node, stored element stiffness" if (prob.model == "linear" and congruent)
+            else "element kernel + slot gather")
+    log(args, f"  matvec {prob.name} {prob.model} {prob.grid}: {us:.2f} us/apply, {achieved:.0f} GB/s ({path})")
+    del graph, ctx
+    return {"us_per_apply": us, "dofs": n3, "elements": prob.n_elems, "path": path, "graph_replay_matches": ok,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_apply": alg}}
+
+
 def run_batch(probs, precision, steps, m_max, stream, torch, args):
     from paper_2405_05213_amd import batch_from_problems
     b = batch_from_problems(probs, m_max=m_max, precision=precision, stream=stream.cuda_stream)
@@ -272,6 +321,15 @@ def main():
                 extra[f"{name}_{prec}"] = {k: v for k, v in r.items() if k not in ("ctx", "step_ms", "energy_rel_err")}
                 extra[f"{name}_{prec}"]["free_dofs"] = p.n_free
                 del r
+        import dataclasses
+        cube = config("c4")
+        for nx in (64, 128):
+            q = cube if nx == 64 else config("c4", nx=nx, ny=nx, nz=nx)
+            q = dataclasses.replace(q, model="linear", params=(200e9, 0.3), rho=7800.0)
+            extra[f"matvec_cube{nx}_linear_f64"] = run_matvec(q, None, 50, stream, torch, args)
+            del q
+        u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
+        extra["matvec_cube64_yeoh_f64"] = run_matvec(cube, u_aff, 20, stream, torch, args)
         probs = batch_instances(256, seed=5, dt=2.5e-5)
         for prec in ("f64", "mixed_f32"):
             extra[f"c5_batch_{prec}"] = run_batch(probs, prec, 30, 32, stream, torch, args)

@@ -178,11 +178,13 @@ ep_status ep_get_stats(ep_ctx* ctx, int64_t* matvecs, int* last_m, double* last_
                        int* last_k, double* aug_drift);
 
 /* Launch layout of the persistent Krylov kernel after binding (or autotuning): the
- * number of workgroups, the Krylov-vector entries each owns, and whether the mesh was
- * found congruent (every element a translate of element 0: J^{-1} and det J agree to
- * 1e-13 at every quadrature point), which selects the stored-element-stiffness path of the
- * linear-elastic operator. */
-ep_status ep_get_launch(ep_ctx* ctx, int* workgroups, int* chunk, int* congruent);
+ * number of workgroups, the Krylov-vector entries each owns, whether those slices live in
+ * device memory (1; meshes too large for them to fit in LDS with one workgroup per
+ * compute unit, or a forced small team) or in LDS (0), and whether the mesh was found
+ * congruent (every element a translate of element 0: J^{-1} and det J agree to 1e-13 at
+ * every quadrature point), which selects the stored-element-stiffness path of the
+ * linear-elastic operator.  Null outputs are skipped. */
+ep_status ep_get_launch(ep_ctx* ctx, int* workgroups, int* chunk, int* slices_global, int* congruent);
 
 /* Per-step log of the last n steps (n <= 4096): m of the corrector and predictor
  * projections (first substep), substep counts and eps.  Arrays of length n. */
@@ -196,7 +198,10 @@ ep_status ep_get_step_log(ep_ctx* ctx, int n, int32_t* m_corr, int32_t* m_pred,
 
 /* y = H(u_lin) x on all 3*n_nodes DOFs (rows and columns of clamped DOFs included;
  * u_lin = NULL means u = 0, i.e. the linear-elastic stiffness).  x_dev, y_dev, u_lin_dev:
- * 3*n_nodes doubles.  Weak-form term 2 (Sec. 2.2) with the secant split (App. A). */
+ * 3*n_nodes doubles.  Weak-form term 2 (Sec. 2.2) with the secant split (App. A).
+ * Enqueued on the context's stream without waiting; an inverted element (secant
+ * materials) is reported by the next ep_sync.  FP64 linear elasticity on a congruent mesh
+ * runs as one node-by-node pass with the stored element stiffness. */
 ep_status ep_apply_H(ep_ctx* ctx, const double* u_lin_dev, const double* x_dev, double* y_dev);
 
 /* y = tau * A x with A the augmented first-order matrix (Sec. 2.3) at load scale

@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
   int* flag = (int*)(lds + 32 + kMaxM);
   // the slice region (lds_slices doubles) doubles as expm scratch: the sequential form
   // reloads both slice buffers after a check point
-  const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, flag + 16};
+  const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, flag + 16, true};
   if (threadIdx.x == 0) *flag = 1;
   __syncthreads();
   const int id = ids[blockIdx.x];

@@ -200,18 +200,25 @@ static long long max_chunk(const ep_ctx* c) {
   return std::max(0LL, (kLdsBytes - fixed) / 16 / 64 * 64);
 }
 
-static int pick_G(const ep_ctx* c, const Inst& I, int* chunk) {
-  const int maxG = std::max(1, c->cus);
-  // the workgroup's slice of the Arnoldi vector (and of the previous basis vector) lives in
-  // LDS: at most max_chunk entries per workgroup
-  const long long mc = std::max(64LL, max_chunk(c));
-  const int Gmin = (int)((I.Lp + mc - 1) / mc);
-  int G = c->G_user > 0 ? c->G_user : (int)std::min<long long>(maxG, std::max<long long>(1, (I.Lp + 2047) / 2048));
-  G = std::max(G, Gmin);
-  G = std::max(1, std::min(G, std::min(I.Lp / 64 > 0 ? I.Lp / 64 : 1, 1024)));
+// Slice size for a team of G, and whether the slices fit in LDS (sg = 0) or must live in
+// device memory (sg = 1: meshes beyond max_chunk entries per workgroup on every CU).
+static int chunk_of(const ep_ctx* c, const Inst& I, int G, int* sg) {
   int C = (I.Lp + G - 1) / G;
   C = (C + 63) / 64 * 64;
-  *chunk = C;
+  *sg = C > std::max(64LL, max_chunk(c)) ? 1 : 0;
+  return C;
+}
+
+static int pick_G(const ep_ctx* c, const Inst& I, int* chunk, int* sg) {
+  const int maxG = std::max(1, c->cus);
+  // the workgroup's slice of the Arnoldi vector (and of the newest basis vector) lives in
+  // LDS when it has at most max_chunk entries; teams grow up to one workgroup per CU for that
+  const long long mc = std::max(64LL, max_chunk(c));
+  const int Gmin = (int)std::min<long long>(maxG, (I.Lp + mc - 1) / mc);
+  int G = c->G_user > 0 ? c->G_user : (int)std::min<long long>(maxG, std::max<long long>(1, (I.Lp + 2047) / 2048));
+  if (c->G_user <= 0) G = std::max(G, Gmin);
+  G = std::max(1, std::min(G, std::min(I.Lp / 64 > 0 ? I.Lp / 64 : 1, 1024)));
+  *chunk = chunk_of(c, I, G, sg);
   return G;
 }
 
@@ -255,7 +262,7 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_pv = L.take(8 * 2 * ((n3 + 255) / 256 + 1));
   I.o_eout = L.take(8 * 4);
   I.o_flags = L.take(4 * 4);
-  I.o_wscr = L.take(c->batch ? 8 * 2 * Lp : 8);
+  I.o_wscr = L.take(8 * 2 * Lp);
   I.o_ke = L.take(8 * 24 * kKeLd);
 }
 
@@ -684,18 +691,19 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
     s = ep_batch_bind(c);
     if (s != EP_OK) return s;
   } else {
-    int chunk = 0;
-    int G = pick_G(c, c->one, &chunk);
+    int chunk = 0, sg = 0;
+    int G = pick_G(c, c->one, &chunk, &sg);
     // cooperative residency: shrink G until it fits
     int bpc = 0;
     for (;;) {
-      EP_HIP(c, expv_max_blocks(c->cfg, c->one.model, chunk, &bpc));
+      EP_HIP(c, expv_max_blocks(c->cfg, c->one.model, chunk, sg, &bpc));
       if ((long long)bpc * c->cus >= G || G == 1) break;
       G = std::max(1, (int)((long long)bpc * c->cus));
-      chunk = ((c->one.Lp + G - 1) / G + 63) / 64 * 64;
+      chunk = chunk_of(c, c->one, G, &sg);
     }
-    if (bpc < 1) return fail(c, EP_ERR_WORKSPACE, "Krylov vector slice does not fit in LDS");
+    if (bpc < 1) return fail(c, EP_ERR_WORKSPACE, "persistent kernel does not fit on a compute unit");
     s = setup_inst(c, c->one, G, chunk, Gmax_of(c));
+    c->one.W.slices_global = sg;
     if (s != EP_OK) return s;
   }
   c->bound = true;
@@ -807,11 +815,12 @@ ep_status ep_get_stats(ep_ctx* c, int64_t* matvecs, int* last_m, double* last_ep
   return EP_OK;
 }
 
-ep_status ep_get_launch(ep_ctx* c, int* workgroups, int* chunk, int* congruent) {
+ep_status ep_get_launch(ep_ctx* c, int* workgroups, int* chunk, int* slices_global, int* congruent) {
   ep_status s = need_bound(c);
   if (s != EP_OK) return s;
   if (workgroups) *workgroups = c->one.W.G;
   if (chunk) *chunk = c->one.W.chunk;
+  if (slices_global) *slices_global = c->one.W.slices_global;
   if (congruent) *congruent = c->one.M.congruent;
   return EP_OK;
 }
@@ -854,7 +863,7 @@ ep_status ep_apply_H(ep_ctx* c, const double* u_lin, const double* x, double* y)
   Inst& I = c->one;
   launch_apply_H(I.M, op_from(u_lin, 1.0, 0.0), c->cfg.prec, x, y, I.W.F, I.W.F32, &I.W.ctrl->err, c->stream);
   EP_HIP(c, hipGetLastError());
-  return ep_sync(c);
+  return EP_OK;   // enqueued; a sticky device error is reported by the next ep_sync
 }
 
 ep_status ep_vector_length(ep_ctx* c, int64_t* len, int64_t* padded) {
@@ -1008,17 +1017,18 @@ ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G
   hipEvent_t e0, e1;
   EP_HIP(c, hipEventCreate(&e0));
   EP_HIP(c, hipEventCreate(&e1));
-  int bestG = I.W.G, bestC = I.W.chunk;
+  int bestG = I.W.G, bestC = I.W.chunk, bestS = I.W.slices_global;
   float best = 1e30f;
   const int Gslots = Gmax_of(c);
   for (int G : cand) {
     if (G > Gslots || G > std::max(1, I.Lp / 64)) continue;
-    int chunk = ((I.Lp + G - 1) / G + 63) / 64 * 64;
-    if (chunk > max_chunk(c)) continue;
+    int sg = 0;
+    const int chunk = chunk_of(c, I, G, &sg);
     int bpc = 0;
-    if (expv_max_blocks(c->cfg, I.model, chunk, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
+    if (expv_max_blocks(c->cfg, I.model, chunk, sg, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
     a.W.G = G;
     a.W.chunk = chunk;
+    a.W.slices_global = sg;
     if (launch_expv(a, c->cfg.prec, c->stream) != hipSuccess) continue;   // warm-up
     (void)hipEventRecord(e0, c->stream);
     bool ok = true;
@@ -1032,6 +1042,7 @@ ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G
       best = ms;
       bestG = G;
       bestC = chunk;
+      bestS = sg;
     }
   }
   (void)hipEventDestroy(e0);
@@ -1040,6 +1051,7 @@ ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G
   if (s != EP_OK) return s;
   I.W.G = bestG;
   I.W.chunk = bestC;
+  I.W.slices_global = bestS;
   if (best_G) *best_G = bestG;
   if (best_ms) *best_ms = best < 1e29f ? best : -1.0;
   return EP_OK;

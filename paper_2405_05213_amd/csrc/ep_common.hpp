@@ -111,6 +111,7 @@ struct KWork {
   int chunk;                  // Krylov-vector entries owned by each workgroup
   double* wscr;               // 2 * Lp: slice buffers in device memory when they exceed LDS
   int ex_cap;                 // doubles of LDS the check point may use for exp(H) (set per launch)
+  int slices_global;          // 1: the slice buffers live in wscr instead of LDS
 };
 
 // Device-side record of one instance of a batch: the stepping state lives on the device so

@@ -511,6 +511,46 @@ __device__ __forceinline__ void elem_force_ke(const Mesh& M, int e, const double
   }
 }
 
+// Force rows of node A, (K x)_{3A+c} = sum over the elements e around A of
+// sum_{b,d} K_e[3a+c][3b+d] x_{3 n_b + d} (a = A's local index in e), for a congruent mesh
+// with K_e in LDS: the 8 lanes of a group take the element slots p, p+8, ... of A and the
+// group sums with a butterfly; every lane returns the three sums.  x = src * scale (times
+// M^{-1/2} when scale_mih).  Every lane of the group must call with the same A.
+__device__ __forceinline__ void node_force_ke(const Mesh& M, int A, const double* src, double scale, bool scale_mih,
+                                              const double* Ke, double (&f)[3]) {
+  const int p = threadIdx.x & 7;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const int q1 = M.inc_ptr[A + 1];
+  for (int q = M.inc_ptr[A] + p; q < q1; q += 8) {
+    const int slot = M.inc[q];
+    const int a = slot / M.n_elems, e = slot - a * M.n_elems;
+    int nd[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) nd[b] = M.conn[(size_t)e * 8 + b];
+    const double* r0 = Ke + (3 * a) * kKeLd;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const size_t g = (size_t)nd[b] * 3 + d;
+        double x = src[g] * scale;
+        if (scale_mih) x *= M.mih[g];
+        s0 += r0[3 * b + d] * x;
+        s1 += r0[kKeLd + 3 * b + d] * x;
+        s2 += r0[2 * kKeLd + 3 * b + d] * x;
+      }
+  }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    s0 += __shfl_xor(s0, o, 64);
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+  }
+  f[0] = s0;
+  f[1] = s1;
+  f[2] = s2;
+}
+
 // sum of element-slot forces of DOF 3*A + c over the elements around node A
 // (slot indices, then forces, are loaded 8 at a time so that the loads overlap)
 template <typename T>

@@ -1,6 +1,7 @@
 // HIP kernels of the exponential propagator for gfx950 and their host launch wrappers.
-#include "ep_kernels.hpp"
-#include "ep_krylov.hpp"
+#include <algorithm>
+
+#include "ep_expv.hpp"
 
 namespace ep {
 
@@ -383,84 +384,27 @@ __global__ __launch_bounds__(256) void k_energy_final(Mesh M, double t, const do
 // ---------------------------------------------------------------------------------------
 // persistent projection kernel: one cooperative launch per exp(tau A) w
 // ---------------------------------------------------------------------------------------
-// LDS: red[32] | yb[kMaxM] | ke[24 kKeLd] | (compact WY: T[m_max^2] | vals[2 m_max] | gp[kThreads]) |
-//      ints: flag[16], ired[16] | union of the slice buffers lw, lv (2 chunk)
-//      and the check point's expm scratch (ex_cap doubles)
-static size_t expv_head_doubles(int ortho, int m_max) {
-  size_t d = 32 + kMaxM + 24 * kKeLd + 16;
-  if (ortho == 1) d += (size_t)m_max * m_max + 2 * (size_t)m_max + kThreads;
-  return d;
-}
-
-template <typename T, int MODEL, int ORTHO>
-__global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
-  extern __shared__ double lds[];
-  const int C = A.W.chunk;
-  const int mm = A.cfg.m_max;
-  double* red = lds;
-  double* yb = red + 32;
-  double* ke = yb + kMaxM;
-  double* p = ke + 24 * kKeLd;
-  KLds X{nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
-  if (MODEL == kLinear && sizeof(T) == 8 && A.M.ke != nullptr) {
-    for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) ke[i] = A.M.ke[i];
-    X.ke = ke;
-  }
-  if (ORTHO == 1) {
-    X.T = p;
-    X.vals = X.T + mm * mm;
-    X.gp = X.vals + 2 * mm;
-    p = X.gp + kThreads;
-  }
-  int* ints = (int*)p;
-  int* flag = ints;
-  X.ired = ints + 16;
-  double* U = p + 16;
-  double* lw = U;
-  double* lv = U + C;
-  X.ex = U;
-  X.ex_cap = A.W.ex_cap;
-  if (threadIdx.x == 0) *flag = 1;   // workgroup alive flag (cleared on a synchronisation timeout)
-  __syncthreads();
-  GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false, 0u,
-              A.W.vring, A.W.vw, 0u};
-  expv_body<T, MODEL, GridTeam, ORTHO>(tm, A, lw, lv, red, yb, flag, X);
-}
-
 constexpr size_t kLdsLimit = 160 * 1024;
 
 size_t expv_lds_head_bytes(int ortho, int m_max) { return expv_head_doubles(ortho, m_max) * sizeof(double); }
 
-size_t expv_lds_bytes(int chunk, int ortho, int m_max) {
+size_t expv_lds_bytes(int chunk, int ortho, int m_max, int sg) {
   const size_t head = expv_lds_head_bytes(ortho, m_max);
   const size_t room = kLdsLimit > head ? kLdsLimit - head : 0;
   const size_t want = (size_t)expm_scratch(m_max) * sizeof(double);
-  size_t u = 2 * (size_t)chunk * sizeof(double);
+  size_t u = sg ? 0 : 2 * (size_t)chunk * sizeof(double);
   const size_t ex = want < room ? want : room;
   if (u < ex) u = ex;
   return head + u;
 }
 
-template <typename T, int MODEL>
-static const void* expv_fn(int ortho) {
-  return ortho == 1 ? reinterpret_cast<const void*>(&k_expv<T, MODEL, 1>)
-                    : reinterpret_cast<const void*>(&k_expv<T, MODEL, 0>);
+static const void* expv_kernel(int prec, int model, int ortho, int sg) {
+  return sg ? expv_kernel_global(prec, model, ortho) : expv_kernel_sg<0>(prec, model, ortho);
 }
 
-static const void* expv_kernel(int prec, int model, int ortho) {
-  if (prec == 0) {
-    if (model == kLinear) return expv_fn<double, kLinear>(ortho);
-    if (model == kNH) return expv_fn<double, kNH>(ortho);
-    return expv_fn<double, kYeoh>(ortho);
-  }
-  if (model == kLinear) return expv_fn<float, kLinear>(ortho);
-  if (model == kNH) return expv_fn<float, kNH>(ortho);
-  return expv_fn<float, kYeoh>(ortho);
-}
-
-hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int* blocks_per_cu) {
-  const void* fn = expv_kernel(cfg.prec, model, cfg.ortho);
-  const size_t lds = expv_lds_bytes(chunk, cfg.ortho, cfg.m_max);
+hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int sg, int* blocks_per_cu) {
+  const void* fn = expv_kernel(cfg.prec, model, cfg.ortho, sg);
+  const size_t lds = expv_lds_bytes(chunk, cfg.ortho, cfg.m_max, sg);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds);
@@ -479,8 +423,8 @@ hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
   const int nv = a.cfg.ortho == 1 ? kRing * a.W.G * a.W.vw : 0;
   const int n = nv > kRing * a.W.G ? nv : kRing * a.W.G;
   k_prep_team<<<(n + 255) / 256, 256, 0, st>>>(a.W.flags, a.W.ring, a.W.vring, a.W.G, nv);
-  const void* fn = expv_kernel(prec, a.M.model, a.cfg.ortho);
-  const size_t lds = expv_lds_bytes(a.W.chunk, a.cfg.ortho, a.cfg.m_max);
+  const void* fn = expv_kernel(prec, a.M.model, a.cfg.ortho, a.W.slices_global);
+  const size_t lds = expv_lds_bytes(a.W.chunk, a.cfg.ortho, a.cfg.m_max, a.W.slices_global);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   ExpvArgs copy = a;
@@ -529,8 +473,28 @@ static void elem_forces_t(const Mesh& M, const OpArgs& op, const double* src, do
   else k_elem_forces<T, kYeoh><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
 }
 
+// y = K x by nodes for a congruent mesh (FP64 linear elasticity): no element-force buffer,
+// one pass; K_e staged in LDS per workgroup, grid-stride over nodes, 8 lanes per node.
+__global__ __launch_bounds__(512) void k_apply_ke(Mesh M, const double* __restrict__ x, double* __restrict__ y) {
+  __shared__ double ke[24 * kKeLd];
+  for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) ke[i] = M.ke[i];
+  __syncthreads();
+  const int groups = (gridDim.x * blockDim.x) >> 3;
+  for (int A = (blockIdx.x * blockDim.x + threadIdx.x) >> 3; A < M.n_nodes; A += groups) {
+    double f[3];
+    node_force_ke(M, A, x, 1.0, false, ke, f);
+    const int p = threadIdx.x & 7;
+    if (p < 3) y[(size_t)A * 3 + p] = p == 0 ? f[0] : (p == 1 ? f[1] : f[2]);
+  }
+}
+
 void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
                     int* err, hipStream_t st) {
+  if (prec == 0 && M.model == kLinear && M.ke != nullptr) {
+    const int blocks = (int)std::min<long long>((M.n_nodes + 63) / 64, 4096);
+    if (blocks > 0) k_apply_ke<<<blocks, 512, 0, st>>>(M, x, y);
+    return;
+  }
   if (prec == 0) {
     elem_forces_t<double>(M, op, x, 1.0, 0, F, err, st);
     k_gather_H<double><<<nblk(M.n3, 256), 256, 0, st>>>(M, F, y);

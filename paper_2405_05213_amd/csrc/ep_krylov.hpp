@@ -49,6 +49,7 @@ struct KLds {
   double* ex;
   int ex_cap;
   int* ired;
+  bool ex_aliases;            // ex overlays the slice buffers (reload v_j after a check)
 };
 
 // Entries of the next basis vector's slice that a thread can hold in registers while a
@@ -448,12 +449,19 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
       double w = lw[t];
       const double* Vt = W.V + c0 + t;
       int k = 0;
-      for (; k + 8 <= j - 1; k += 8) {
-        double q[8];
+      for (; k + 16 <= j - 1; k += 16) {
+        double q[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) q[u] = Vt[(size_t)(k + u) * Lp];
+        for (int u = 0; u < 16; ++u) q[u] = Vt[(size_t)(k + u) * Lp];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) w -= yb[k + u] * q[u];
+        for (int u = 0; u < 16; ++u) w -= yb[k + u] * q[u];
+      }
+      for (; k + 4 <= j - 1; k += 4) {
+        double q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = Vt[(size_t)(k + u) * Lp];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w -= yb[k + u] * q[u];
       }
       for (; k < j - 1; ++k) w -= yb[k] * Vt[(size_t)k * Lp];
       w -= yb[j - 1] * lv[t];
@@ -483,7 +491,7 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     if (check) {
       const int c = check_point(tm, A, j, hn, beta, breakdown, red, yb, X, flag, nloc, c0, R);
       if (c != 0) return R;
-      if (lead && X.ex != nullptr && expm_scratch(j) <= X.ex_cap) {
+      if (lead && X.ex_aliases && X.ex != nullptr && expm_scratch(j) <= X.ex_cap) {
         // exp(H_j) overwrote the slice buffers of workgroup 0: reload v_j (w is rebuilt)
         const double* Vj = W.V + (size_t)j * Lp + c0;
         for (int t = threadIdx.x; t < nloc; t += blockDim.x) lv[t] = Vj[t];

@@ -44,7 +44,7 @@ _SIGS = {
     "ep_set_krylov": [_vp, _dbl, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dbl],
     "ep_set_precision": [_vp, C.c_int],
     "ep_set_orthogonalization": [_vp, C.c_int],
-    "ep_get_launch": [_vp, _P(C.c_int), _P(C.c_int), _P(C.c_int)],
+    "ep_get_launch": [_vp, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)],
     "ep_get_orthogonalization": [_vp, _P(C.c_int)],
     "ep_set_launch": [_vp, C.c_int],
     "ep_autotune": [_vp, _dbl, C.c_int, C.c_int, _P(C.c_int), _P(_dbl)],
@@ -175,9 +175,14 @@ class Context:
 
     def launch(self):
         """(workgroups, entries per workgroup, congruent mesh) of the persistent kernel."""
-        g, ch, cg = C.c_int(), C.c_int(), C.c_int()
-        self._call("ep_get_launch", C.byref(g), C.byref(ch), C.byref(cg))
+        g, ch, sg, cg = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        self._call("ep_get_launch", C.byref(g), C.byref(ch), C.byref(sg), C.byref(cg))
         return g.value, ch.value, bool(cg.value)
+
+    def slices_in_device_memory(self) -> bool:
+        sg = C.c_int()
+        self._call("ep_get_launch", None, None, C.byref(sg), None)
+        return bool(sg.value)
 
     def set_launch(self, workgroups: int):
         self._call("ep_set_launch", int(workgroups))
@@ -241,8 +246,10 @@ class Context:
         self._call("ep_vector_length", C.byref(a), C.byref(b))
         return a.value, b.value
 
-    def apply_H(self, u_lin, x, y):
+    def apply_H(self, u_lin, x, y, sync=True):
         self._call("ep_apply_H", _ptr(u_lin), _ptr(x), _ptr(y))
+        if sync:
+            self.sync()
 
     def apply_A(self, u_lin, tau, pscale, x, y):
         self._call("ep_apply_A", _ptr(u_lin), float(tau), float(pscale), _ptr(x), _ptr(y))

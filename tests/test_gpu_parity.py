@@ -185,3 +185,23 @@ def test_energy_conservation_free_vibration(prec, tol):
     e1 = ctx.energy()
     E0, E1 = e0[0] + e0[1] - e0[2], e1[0] + e1[1] - e1[2]
     assert abs(E1 - E0) <= tol * (e0[0] + e0[1])
+
+
+@pytest.mark.parametrize("ortho", [0, 1])
+def test_slices_in_device_memory(ortho):
+    """A team too small for its Krylov-vector slices to fit in LDS keeps them in device
+    memory: same steps as the oracle (and the LDS layout) on a 40x8x8 cantilever."""
+    say(f"[slices in device memory] ortho={ortho}")
+    p = config("c2", nx=40, ny=8, nz=8)
+    ctx, orc = pair(p, m_max=48, workgroups=2, ortho=ortho)
+    assert ctx.slices_in_device_memory()
+    ref, _ = pair(p, m_max=48, ortho=ortho)
+    assert not ref.slices_in_device_memory()
+    n = 3
+    ctx.step(p.dt, n)
+    ref.step(p.dt, n)
+    orc.run(p.dt, n)
+    _, u, v = ctx.get_state()
+    _, ur, vr = ref.get_state()
+    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
+    assert rel(u, ur) < 1e-9 and rel(v, vr) < 1e-9
