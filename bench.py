@@ -183,7 +183,8 @@ def run_matvec(prob, u_lin, reps, stream, torch, args):
     graph on a side stream (a single apply takes less time than a host-side launch), the
     graph is replayed and timed with events; the replayed result is checked against the
     eager one.  Algorithmic bytes of one apply: read x and write y (3 n_n doubles each),
-    read the connectivity (32 B per element), plus u (3 n_n doubles) for a secant material."""
+    plus the connectivity (32 B per element) on paths that read it, plus u (3 n_n doubles)
+    for a secant material."""
     from paper_2405_05213_amd import solver_from_problem
     side = torch.cuda.Stream()
     ctx = solver_from_problem(prob, m_max=4, stream=side.cuda_stream)
@@ -215,11 +216,15 @@ def run_matvec(prob, u_lin, reps, stream, torch, args):
     side.synchronize()
     ctx.sync()
     us = e0.elapsed_time(e1) * 1e3 / (rounds * reps)
-    alg = (2 * n3 + (n3 if u is not None else 0)) * 8 + 32 * prob.n_elems
+    workgroups, chunk, mesh_class = ctx.launch()
+    if prob.model == "linear" and mesh_class == 2:
+        path, reads_conn = "lattice: 27-block stencil over LDS tiles + boundary faces", False
+    elif prob.model == "linear" and mesh_class == 1:
+        path, reads_conn = "node-by-node, stored element stiffness", True
+    else:
+        path, reads_conn = "element kernel + slot gather", True
+    alg = (2 * n3 + (n3 if u is not None else 0)) * 8 + (32 * prob.n_elems if reads_conn else 0)
     achieved = alg / (us * 1e-6) / 1e9
-    workgroups, chunk, congruent = ctx.launch()
-    path = ("node-by-node, stored element stiffness" if (prob.model == "linear" and congruent)
-            else "element kernel + slot gather")
     log(args, f"  matvec {prob.name} {prob.model} {prob.grid}: {us:.2f} us/apply, {achieved:.0f} GB/s ({path})")
     del graph, ctx
     return {"us_per_apply": us, "dofs": n3, "elements": prob.n_elems, "path": path, "graph_replay_matches": ok,

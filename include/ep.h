@@ -185,6 +185,9 @@ ep_status ep_get_stats(ep_ctx* ctx, int64_t* matvecs, int* last_m, double* last_
  * every quadrature point), which selects the stored-element-stiffness path of the
  * linear-elastic operator.  Null outputs are skipped. */
 ep_status ep_get_launch(ep_ctx* ctx, int* workgroups, int* chunk, int* slices_global, int* congruent);
+/* (congruent: 0 general mesh, 1 congruent, 2 congruent lattice -- node (i, j, k) numbered
+ * i + (nx+1)(j + (ny+1)k), elements i-fastest, VTK corner order -- whose FP64 linear
+ * operator apply (ep_apply_H) runs as a 27-block stencil over LDS tiles) */
 
 /* Per-step log of the last n steps (n <= 4096): m of the corrector and predictor
  * projections (first substep), substep counts and eps.  Arrays of length n. */

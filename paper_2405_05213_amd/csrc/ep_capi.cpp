@@ -54,6 +54,7 @@ struct Inst {
   // workspace offsets
   size_t o_xyz, o_conn, o_incp, o_inc, o_geo, o_geo32, o_vdet, o_mih, o_mh, o_p0, o_p0bar, o_faces, o_fincp,
       o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y, o_ke,
+      o_stencil,
       o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr;
   Mesh M{};
   KWork W{};
@@ -264,6 +265,7 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_flags = L.take(4 * 4);
   I.o_wscr = L.take(8 * 2 * Lp);
   I.o_ke = L.take(8 * 24 * kKeLd);
+  I.o_stencil = L.take(8 * 27 * 9);
 }
 
 static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
@@ -316,6 +318,31 @@ static double auto_s0(const ep_ctx* c, const Inst& I) {
   bool nonzero_scale = false;
   for (int i = 0; i < I.n_knots; ++i) nonzero_scale |= I.knots[I.n_knots + i] != 0.0;
   return (load && nonzero_scale) ? 1.0 : 0.0;
+}
+
+// A structured box: node (i, j, k) = i + (nx+1)(j + (ny+1)k), elements in i-fastest order
+// with VTK corner order.  Read off element 0 and verified on every element.
+static bool lattice_dims(const Inst& I, int lat[3]) {
+  if (I.n_elems < 1) return false;
+  const int32_t* c0 = I.conn.data();
+  const int64_t sx = c0[3] - c0[0], sxy = c0[4] - c0[0];
+  if (c0[0] != 0 || c0[1] != 1 || sx < 2 || sxy % sx != 0) return false;
+  const int64_t nx = sx - 1, ny = sxy / sx - 1;
+  if (ny < 1 || I.n_elems % (nx * ny) != 0) return false;
+  const int64_t nz = I.n_elems / (nx * ny);
+  if ((nx + 1) * (ny + 1) * (nz + 1) != I.n_nodes) return false;
+  static const int di[8] = {0, 1, 1, 0, 0, 1, 1, 0}, dj[8] = {0, 0, 1, 1, 0, 0, 1, 1}, dk[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+  for (int64_t e = 0; e < I.n_elems; ++e) {
+    const int64_t i = e % nx, j = (e / nx) % ny, k = e / (nx * ny);
+    for (int a = 0; a < 8; ++a) {
+      const int64_t n = (i + di[a]) + (nx + 1) * ((j + dj[a]) + (ny + 1) * (k + dk[a]));
+      if (I.conn[(size_t)e * 8 + a] != n) return false;
+    }
+  }
+  lat[0] = (int)nx;
+  lat[1] = (int)ny;
+  lat[2] = (int)nz;
+  return true;
 }
 
 static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
@@ -379,10 +406,19 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   M.s0 = auto_s0(c, I);
   M.s_inv = M.s0 != 0.0 ? 1.0 / M.s0 : 0.0;
   M.ke = nullptr;
+  M.lat[0] = M.lat[1] = M.lat[2] = 0;
+  M.stencil = nullptr;
   if (M.congruent && I.n_elems > 0) {
     launch_stiffness(M, dptr<double>(c, I.o_ke), st);
     EP_HIP(c, hipGetLastError());
     M.ke = dptr<double>(c, I.o_ke);
+    int lat[3];
+    if (lattice_dims(I, lat)) {
+      launch_stencil_blocks(M.ke, dptr<double>(c, I.o_stencil), st);
+      EP_HIP(c, hipGetLastError());
+      for (int d = 0; d < 3; ++d) M.lat[d] = lat[d];
+      M.stencil = dptr<double>(c, I.o_stencil);
+    }
   }
   KWork& W = I.W;
   W.V = dptr<double>(c, I.o_V);
@@ -821,7 +857,7 @@ ep_status ep_get_launch(ep_ctx* c, int* workgroups, int* chunk, int* slices_glob
   if (workgroups) *workgroups = c->one.W.G;
   if (chunk) *chunk = c->one.W.chunk;
   if (slices_global) *slices_global = c->one.W.slices_global;
-  if (congruent) *congruent = c->one.M.congruent;
+  if (congruent) *congruent = c->one.M.congruent ? (c->one.M.lat[0] > 0 ? 2 : 1) : 0;
   return EP_OK;
 }
 

@@ -33,6 +33,9 @@ struct Mesh {
   int congruent;              // 1: one geometry set shared by all elements
   const double* ke;           // congruent meshes: rest-state element stiffness (24 x kKeLd),
                               // null otherwise
+  int lat[3];                 // congruent lattice (node i + (nx+1)(j + (ny+1)k), VTK order):
+                              // nx, ny, nz; zeros otherwise
+  const double* stencil;      // lattice: the 27 3x3 blocks of an interior node's rows of K
   const double* mih;          // M^{-1/2} per DOF (0 on clamped DOFs)
   const double* mh;           // M^{1/2}  per DOF (0 on clamped DOFs)
   const double* p0bar;        // M^{-1/2} P0 per DOF (0 on clamped DOFs)

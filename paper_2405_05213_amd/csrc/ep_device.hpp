@@ -511,6 +511,11 @@ __device__ __forceinline__ void elem_force_ke(const Mesh& M, int e, const double
   }
 }
 
+// VTK corner c of a hex as offsets (di, dj, dk) in {0, 1}^3
+__host__ __device__ __forceinline__ int vtk_di(int c) { return (c == 1 || c == 2 || c == 5 || c == 6) ? 1 : 0; }
+__host__ __device__ __forceinline__ int vtk_dj(int c) { return (c == 2 || c == 3 || c == 6 || c == 7) ? 1 : 0; }
+__host__ __device__ __forceinline__ int vtk_dk(int c) { return c >= 4 ? 1 : 0; }
+
 // Force rows of node A, (K x)_{3A+c} = sum over the elements e around A of
 // sum_{b,d} K_e[3a+c][3b+d] x_{3 n_b + d} (a = A's local index in e), for a congruent mesh
 // with K_e in LDS: the 8 lanes of a group take the element slots p, p+8, ... of A and the

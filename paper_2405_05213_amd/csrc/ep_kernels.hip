@@ -488,8 +488,151 @@ __global__ __launch_bounds__(512) void k_apply_ke(Mesh M, const double* __restri
   }
 }
 
+// The 27 3x3 blocks of an interior lattice node's rows of K, B_o = sum over the elements
+// holding both the node and its neighbour at offset o of the corresponding K_e block; fixed
+// element order.  One thread per (o, i, j).
+__global__ void k_stencil_blocks(const double* __restrict__ Ke, double* __restrict__ B) {
+  const int t = threadIdx.x;
+  if (t >= 27 * 9) return;
+  const int o = t / 9, i = (t % 9) / 3, j = t % 3;
+  const int oi = o % 3 - 1, oj = (o / 3) % 3 - 1, ok = o / 9 - 1;
+  double s = 0.0;
+  for (int e = 0; e < 8; ++e) {
+    // element whose corner (ci, cj, ck) is the node: its lowest corner is node - (ci, cj, ck)
+    const int ci = e & 1, cj = (e >> 1) & 1, ck = e >> 2;
+    int a = -1, b = -1;
+    for (int c = 0; c < 8; ++c) {
+      if (vtk_di(c) == ci && vtk_dj(c) == cj && vtk_dk(c) == ck) a = c;
+      if (vtk_di(c) == ci + oi && vtk_dj(c) == cj + oj && vtk_dk(c) == ck + ok) b = c;
+    }
+    if (b >= 0) s += Ke[(3 * a + i) * kKeLd + 3 * b + j];
+  }
+  B[t] = s;
+}
+
+void launch_stencil_blocks(const double* Ke, double* B, hipStream_t st) { k_stencil_blocks<<<1, 256, 0, st>>>(Ke, B); }
+
+// y = K x on a congruent lattice, interior nodes: a workgroup takes a TX x TY x TZ block of
+// nodes and stages x over the block and its one-node halo in LDS (one array per component);
+// each interior node applies the 27 blocks B_o, whose addresses are uniform (scalar loads).
+// Nodes on the lattice boundary are left to k_apply_lattice_bnd.
+constexpr int kTX = 16, kTY = 8, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHN = kHX * kHY * kHZ;
+
+__global__ __launch_bounds__(kTX * kTY * kTZ) void k_apply_lattice(Mesh M, const double* __restrict__ x,
+                                                                 double* __restrict__ y) {
+  __shared__ double xs[3][kHN];
+  const int nx = M.lat[0], ny = M.lat[1], nz = M.lat[2];
+  const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+  const int bx = (NX + kTX - 1) / kTX, by = (NY + kTY - 1) / kTY;
+  const int blk = blockIdx.x;
+  const int i0 = (blk % bx) * kTX, j0 = ((blk / bx) % by) * kTY, k0 = (blk / (bx * by)) * kTZ;
+  // halo rows (hj, hk) of kHX nodes: 64 lanes per row, 8 rows at a time
+  const int lane = threadIdx.x & 63;
+  for (int row = threadIdx.x >> 6; row < kHY * kHZ; row += blockDim.x >> 6) {
+    const int hj = row % kHY, hk = row / kHY;
+    const int gj = j0 - 1 + hj, gk = k0 - 1 + hk;
+    const bool okr = gj >= 0 && gj < NY && gk >= 0 && gk < NZ;
+    const size_t base = ((size_t)NX * ((size_t)gj + (size_t)NY * gk)) * 3;
+    if (lane < 3 * kHX) {
+      const int hi = lane / 3, c = lane - 3 * (lane / 3);
+      const int gi = i0 - 1 + hi;
+      double v = 0.0;
+      if (okr && gi >= 0 && gi < NX) v = x[base + (size_t)gi * 3 + c];
+      xs[c][hi + kHX * row] = v;
+    }
+  }
+  __syncthreads();
+  const int ti = threadIdx.x % kTX, tj = (threadIdx.x / kTX) % kTY, tk = threadIdx.x / (kTX * kTY);
+  const int i = i0 + ti, j = j0 + tj, k = k0 + tk;
+  if (!(i > 0 && i < nx && j > 0 && j < ny && k > 0 && k < nz)) return;
+  const int hc = (ti + 1) + kHX * ((tj + 1) + kHY * (tk + 1));
+  const double* __restrict__ B = M.stencil;
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+  for (int o = 0; o < 27; ++o) {
+    const int h = hc + (o % 3 - 1) + kHX * ((o / 3) % 3 - 1) + kHX * kHY * (o / 9 - 1);
+    const double x0 = xs[0][h], x1 = xs[1][h], x2 = xs[2][h];
+    f0 = fma(B[9 * o + 0], x0, f0);
+    f1 = fma(B[9 * o + 3], x0, f1);
+    f2 = fma(B[9 * o + 6], x0, f2);
+    f0 = fma(B[9 * o + 1], x1, f0);
+    f1 = fma(B[9 * o + 4], x1, f1);
+    f2 = fma(B[9 * o + 7], x1, f2);
+    f0 = fma(B[9 * o + 2], x2, f0);
+    f1 = fma(B[9 * o + 5], x2, f1);
+    f2 = fma(B[9 * o + 8], x2, f2);
+  }
+  const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
+  y[3 * n] = f0;
+  y[3 * n + 1] = f1;
+  y[3 * n + 2] = f2;
+}
+
+// Nodes on the lattice boundary: the faces k = 0, nz (all i, j), then j = 0, ny (0 < k < nz),
+// then i = 0, nx (0 < j < ny, 0 < k < nz), each node once; K_e rows summed over the
+// node's existing elements, inputs read from device memory.
+__global__ __launch_bounds__(256) void k_apply_lattice_bnd(Mesh M, const double* __restrict__ x,
+                                                          double* __restrict__ y) {
+  __shared__ double ke[24 * kKeLd];
+  for (int t = threadIdx.x; t < 24 * kKeLd; t += blockDim.x) ke[t] = M.ke[t];
+  __syncthreads();
+  const int nx = M.lat[0], ny = M.lat[1], nz = M.lat[2];
+  const long long NX = nx + 1, NY = ny + 1;
+  const long long nk = 2 * NX * NY, nj = 2 * NX * (nz - 1), ni = 2 * (NY - 2) * (nz - 1);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < nk) {
+    const long long r = t % (NX * NY);
+    i = (int)(r % NX);
+    j = (int)(r / NX);
+    k = t < NX * NY ? 0 : nz;
+  } else if (t < nk + nj) {
+    const long long u = t - nk, r = u % (NX * (nz - 1));
+    i = (int)(r % NX);
+    k = 1 + (int)(r / NX);
+    j = u < NX * (nz - 1) ? 0 : ny;
+  } else if (t < nk + nj + ni) {
+    const long long u = t - nk - nj, r = u % ((NY - 2) * (nz - 1));
+    j = 1 + (int)(r % (NY - 2));
+    k = 1 + (int)(r / (NY - 2));
+    i = u < (NY - 2) * (nz - 1) ? 0 : nx;
+  } else {
+    return;
+  }
+  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+  for (int e = 0; e < 8; ++e) {
+    const int ci = e & 1, cj = (e >> 1) & 1, ck = e >> 2;
+    const int ei = i - ci, ej = j - cj, ek = k - ck;            // lowest corner of the element
+    if (ei < 0 || ei >= nx || ej < 0 || ej >= ny || ek < 0 || ek >= nz) continue;
+    int a = 0;
+    for (int c = 0; c < 8; ++c)
+      if (vtk_di(c) == ci && vtk_dj(c) == cj && vtk_dk(c) == ck) a = c;
+    for (int b = 0; b < 8; ++b) {
+      const size_t nb = (size_t)(ei + vtk_di(b)) + (size_t)NX * ((size_t)(ej + vtk_dj(b)) + (size_t)NY * (ek + vtk_dk(b)));
+      const double* r = ke + (3 * a) * kKeLd + 3 * b;
+      const double x0 = x[3 * nb], x1 = x[3 * nb + 1], x2 = x[3 * nb + 2];
+      f0 = fma(r[0], x0, fma(r[1], x1, fma(r[2], x2, f0)));
+      f1 = fma(r[kKeLd], x0, fma(r[kKeLd + 1], x1, fma(r[kKeLd + 2], x2, f1)));
+      f2 = fma(r[2 * kKeLd], x0, fma(r[2 * kKeLd + 1], x1, fma(r[2 * kKeLd + 2], x2, f2)));
+    }
+  }
+  const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
+  y[3 * n] = f0;
+  y[3 * n + 1] = f1;
+  y[3 * n + 2] = f2;
+}
+
 void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
                     int* err, hipStream_t st) {
+  if (prec == 0 && M.model == kLinear && M.lat[0] > 0 && M.stencil != nullptr) {
+    const long long nb = (long long)((M.lat[0] + kTX) / kTX) * ((M.lat[1] + kTY) / kTY) * ((M.lat[2] + kTZ) / kTZ);
+    k_apply_lattice<<<(int)nb, kTX * kTY * kTZ, 0, st>>>(M, x, y);
+    const long long NX = M.lat[0] + 1, NY = M.lat[1] + 1, nz = M.lat[2];
+    const long long nbnd = 2 * NX * NY + 2 * NX * (nz - 1) + 2 * (NY - 2) * (nz - 1);
+    k_apply_lattice_bnd<<<nblk(nbnd, 256), 256, 0, st>>>(M, x, y);
+    return;
+  }
   if (prec == 0 && M.model == kLinear && M.ke != nullptr) {
     const int blocks = (int)std::min<long long>((M.n_nodes + 63) / 64, 4096);
     if (blocks > 0) k_apply_ke<<<blocks, 512, 0, st>>>(M, x, y);

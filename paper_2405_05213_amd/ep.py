@@ -174,10 +174,10 @@ class Context:
         return m.value
 
     def launch(self):
-        """(workgroups, entries per workgroup, congruent mesh) of the persistent kernel."""
+        """(workgroups, entries per workgroup, mesh class: 0 general, 1 congruent, 2 lattice)."""
         g, ch, sg, cg = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         self._call("ep_get_launch", C.byref(g), C.byref(ch), C.byref(sg), C.byref(cg))
-        return g.value, ch.value, bool(cg.value)
+        return g.value, ch.value, cg.value
 
     def slices_in_device_memory(self) -> bool:
         sg = C.c_int()

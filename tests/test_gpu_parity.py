@@ -23,6 +23,8 @@ def _np(t):
 CASES_H = [
     ("linear", "c1", {}, False),
     ("linear", "c1", {}, True),
+    ("linear", "c1", {}, "renumbered"),
+    ("linear", "c1", dict(nx=19, ny=9, nz=5), False),
     ("nh", "c3", dict(nx=8, ny=2, nz=2), False),
     ("nh", "c3", dict(nx=8, ny=2, nz=2), True),
     ("yeoh", "c4", dict(nx=4, ny=3, nz=3), True),
@@ -35,7 +37,9 @@ def test_apply_H_matches_oracle(model, name, over, distorted, prec):
     """Operator apply (weak-form term 2 with the secant split): y = H(u) x on all DOFs."""
     say(f"[apply_H] {model} {name} {over} distorted={distorted} prec={prec}")
     p = config(name, **over)
-    if distorted:
+    if distorted == "renumbered":
+        p = renumbered(p)
+    elif distorted:
         p = distort(p, 0.2, seed=5)
     ctx, orc = pair(p, precision=prec)
     rng = np.random.default_rng(3)
@@ -157,14 +161,31 @@ def test_nonlinear_steps(model, name, over, mode, ortho):
     assert abs(se - so_) <= 1e-8 * (ko + so_ + abs(wo))
 
 
-@pytest.mark.parametrize("name,over,distorted,expect", [("c1", {}, False, True), ("c2", dict(nx=20, ny=4, nz=4), False, True),
-                                                        ("c1", {}, True, False)])
-def test_congruence_detection(name, over, distorted, expect):
-    """Box meshes with coordinates i*h (rounding noise in J) are congruent; distorted are not."""
-    say(f"[congruence] {name} {over} distorted={distorted}")
+def renumbered(p, seed=9):
+    """The same mesh with a random node numbering: congruent, not a lattice."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(p.n_nodes)            # new id of old node
+    inv = np.argsort(perm)
+    clamped = np.sort(3 * perm[np.asarray(p.clamped) // 3] + np.asarray(p.clamped) % 3) if len(p.clamped) else p.clamped
+    faces = perm[np.asarray(p.faces)] if len(p.faces) else p.faces
+    def vec(v):
+        return np.asarray(v).reshape(-1, 3)[inv].ravel()
+    return dataclasses.replace(p, xyz=p.xyz[inv], conn=perm[p.conn].astype(p.conn.dtype), clamped=clamped,
+                               faces=faces, u0=vec(p.u0), v0=vec(p.v0), grid=None)
+
+
+@pytest.mark.parametrize("name,over,mode,expect", [("c1", {}, "box", 2), ("c2", dict(nx=20, ny=4, nz=4), "box", 2),
+                                                   ("c1", {}, "renumbered", 1), ("c1", {}, "distorted", 0)])
+def test_congruence_detection(name, over, mode, expect):
+    """Box meshes with coordinates i*h (rounding noise in J) are congruent lattices; a random
+    renumbering stays congruent but is no lattice; distorted meshes are neither."""
+    say(f"[congruence] {name} {over} {mode}")
     p = config(name, **over)
-    if distorted:
+    if mode == "distorted":
         p = distort(p, 0.2, seed=5)
+    elif mode == "renumbered":
+        p = renumbered(p)
     ctx, _ = pair(p)
     g, chunk, cong = ctx.launch()
     assert cong == expect
