@@ -6,7 +6,10 @@
 
 namespace ep {
 
-constexpr int kThreads = 512;        // workgroup size of every persistent / element kernel
+constexpr int kThreads = 512;        // workgroup size of the batch, expm and element kernels
+constexpr int kExpvThreads = 512;    // workgroup size of the persistent projection kernel (256
+                                     // removes its scratch spills, one wave per SIMD, but is
+                                     // slower on every single-instance workload)
 constexpr int kMaxM = 256;           // largest Krylov subspace
 constexpr int kLogSteps = 4096;      // per-step statistics ring
 constexpr int kMaxKnots = 4096;

@@ -13,14 +13,14 @@ namespace ep {
 //      overlaid with the check point's expm scratch (ex_cap doubles)
 __host__ __device__ inline size_t expv_head_doubles(int ortho, int m_max) {
   size_t d = 32 + kMaxM + 24 * kKeLd + 16;
-  if (ortho == 1) d += (size_t)m_max * m_max + 2 * (size_t)m_max + kThreads;
+  if (ortho == 1) d += (size_t)m_max * m_max + 2 * (size_t)m_max + kExpvThreads;
   return d;
 }
 
 // SG = 1: the workgroup's slices of w and of the newest basis vector live in device memory
 // (W.wscr, [w | v] rows of Lp doubles) and U holds only the expm scratch.
 template <typename T, int MODEL, int ORTHO, int SG>
-__global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
+__global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   extern __shared__ double lds[];
   const int C = A.W.chunk;
   const int mm = A.cfg.m_max;
@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kThreads) void k_expv(ExpvArgs A) {
     X.T = p;
     X.vals = X.T + mm * mm;
     X.gp = X.vals + 2 * mm;
-    p = X.gp + kThreads;
+    p = X.gp + kExpvThreads;
   }
   int* ints = (int*)p;
   int* flag = ints;

@@ -407,7 +407,7 @@ hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int sg, i
   const size_t lds = expv_lds_bytes(chunk, cfg.ortho, cfg.m_max, sg);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kExpvThreads, lds);
 }
 
 // empty all-reduce rings and zero barrier flags of a team before a launch
@@ -430,7 +430,7 @@ hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
   ExpvArgs copy = a;
   copy.W.ex_cap = (int)((lds - expv_lds_head_bytes(a.cfg.ortho, a.cfg.m_max)) / sizeof(double));
   void* args[] = {&copy};
-  return hipLaunchCooperativeKernel(fn, dim3(a.W.G), dim3(kThreads), args, (unsigned)lds, st);
+  return hipLaunchCooperativeKernel(fn, dim3(a.W.G), dim3(kExpvThreads), args, (unsigned)lds, st);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -527,20 +527,27 @@ __global__ __launch_bounds__(kTX * kTY * kTZ) void k_apply_lattice(Mesh M, const
   const int bx = (NX + kTX - 1) / kTX, by = (NY + kTY - 1) / kTY;
   const int blk = blockIdx.x;
   const int i0 = (blk % bx) * kTX, j0 = ((blk / bx) % by) * kTY, k0 = (blk / (bx * by)) * kTZ;
-  // halo rows (hj, hk) of kHX nodes: 64 lanes per row, 8 rows at a time
-  const int lane = threadIdx.x & 63;
-  for (int row = threadIdx.x >> 6; row < kHY * kHZ; row += blockDim.x >> 6) {
+  // halo rows (hj, hk) of kHX nodes (3 kHX doubles, one wave per row): every load of the
+  // thread is issued before the first LDS store
+  constexpr int kRows = kHY * kHZ, kWaves = kTX * kTY * kTZ / 64, kPer = (kRows + kWaves - 1) / kWaves;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int hi = lane / 3, c = lane - 3 * (lane / 3);
+  const int gi = i0 - 1 + hi;
+  const bool oki = lane < 3 * kHX && gi >= 0 && gi < NX;
+  double v[kPer];
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int row = wv + kWaves * r;
     const int hj = row % kHY, hk = row / kHY;
     const int gj = j0 - 1 + hj, gk = k0 - 1 + hk;
-    const bool okr = gj >= 0 && gj < NY && gk >= 0 && gk < NZ;
-    const size_t base = ((size_t)NX * ((size_t)gj + (size_t)NY * gk)) * 3;
-    if (lane < 3 * kHX) {
-      const int hi = lane / 3, c = lane - 3 * (lane / 3);
-      const int gi = i0 - 1 + hi;
-      double v = 0.0;
-      if (okr && gi >= 0 && gi < NX) v = x[base + (size_t)gi * 3 + c];
-      xs[c][hi + kHX * row] = v;
-    }
+    v[r] = 0.0;
+    if (row < kRows && oki && gj >= 0 && gj < NY && gk >= 0 && gk < NZ)
+      v[r] = x[((size_t)gi + (size_t)NX * ((size_t)gj + (size_t)NY * gk)) * 3 + c];
+  }
+#pragma unroll
+  for (int r = 0; r < kPer; ++r) {
+    const int row = wv + kWaves * r;
+    if (row < kRows && lane < 3 * kHX) xs[c][hi + kHX * row] = v[r];
   }
   __syncthreads();
   const int ti = threadIdx.x % kTX, tj = (threadIdx.x / kTX) % kTY, tk = threadIdx.x / (kTX * kTY);
@@ -570,8 +577,9 @@ __global__ __launch_bounds__(kTX * kTY * kTZ) void k_apply_lattice(Mesh M, const
 }
 
 // Nodes on the lattice boundary: the faces k = 0, nz (all i, j), then j = 0, ny (0 < k < nz),
-// then i = 0, nx (0 < j < ny, 0 < k < nz), each node once; K_e rows summed over the
-// node's existing elements, inputs read from device memory.
+// then i = 0, nx (0 < j < ny, 0 < k < nz), each node once.  Eight lanes per node, lane e
+// applies the node's K_e rows of the e-th surrounding element (if it exists) to that
+// element's inputs (device memory); a butterfly sums the eight.
 __global__ __launch_bounds__(256) void k_apply_lattice_bnd(Mesh M, const double* __restrict__ x,
                                                           double* __restrict__ y) {
   __shared__ double ke[24 * kKeLd];
@@ -580,7 +588,8 @@ __global__ __launch_bounds__(256) void k_apply_lattice_bnd(Mesh M, const double*
   const int nx = M.lat[0], ny = M.lat[1], nz = M.lat[2];
   const long long NX = nx + 1, NY = ny + 1;
   const long long nk = 2 * NX * NY, nj = 2 * NX * (nz - 1), ni = 2 * (NY - 2) * (nz - 1);
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 3;   // uniform per 8 lanes
+  const int e = threadIdx.x & 7;
   int i, j, k;
   if (t < nk) {
     const long long r = t % (NX * NY);
@@ -598,29 +607,40 @@ __global__ __launch_bounds__(256) void k_apply_lattice_bnd(Mesh M, const double*
     k = 1 + (int)(r / (NY - 2));
     i = u < (NY - 2) * (nz - 1) ? 0 : nx;
   } else {
-    return;
+    return;                                    // whole 8-lane groups leave together
   }
   double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-  for (int e = 0; e < 8; ++e) {
-    const int ci = e & 1, cj = (e >> 1) & 1, ck = e >> 2;
-    const int ei = i - ci, ej = j - cj, ek = k - ck;            // lowest corner of the element
-    if (ei < 0 || ei >= nx || ej < 0 || ej >= ny || ek < 0 || ek >= nz) continue;
+  const int ci = e & 1, cj = (e >> 1) & 1, ck = e >> 2;
+  const int ei = i - ci, ej = j - cj, ek = k - ck;              // lowest corner of the element
+  if (ei >= 0 && ei < nx && ej >= 0 && ej < ny && ek >= 0 && ek < nz) {
     int a = 0;
     for (int c = 0; c < 8; ++c)
       if (vtk_di(c) == ci && vtk_dj(c) == cj && vtk_dk(c) == ck) a = c;
+    double xe[24];
+#pragma unroll
     for (int b = 0; b < 8; ++b) {
       const size_t nb = (size_t)(ei + vtk_di(b)) + (size_t)NX * ((size_t)(ej + vtk_dj(b)) + (size_t)NY * (ek + vtk_dk(b)));
+      xe[3 * b] = x[3 * nb];
+      xe[3 * b + 1] = x[3 * nb + 1];
+      xe[3 * b + 2] = x[3 * nb + 2];
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
       const double* r = ke + (3 * a) * kKeLd + 3 * b;
-      const double x0 = x[3 * nb], x1 = x[3 * nb + 1], x2 = x[3 * nb + 2];
+      const double x0 = xe[3 * b], x1 = xe[3 * b + 1], x2 = xe[3 * b + 2];
       f0 = fma(r[0], x0, fma(r[1], x1, fma(r[2], x2, f0)));
       f1 = fma(r[kKeLd], x0, fma(r[kKeLd + 1], x1, fma(r[kKeLd + 2], x2, f1)));
       f2 = fma(r[2 * kKeLd], x0, fma(r[2 * kKeLd + 1], x1, fma(r[2 * kKeLd + 2], x2, f2)));
     }
   }
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+    f0 += __shfl_xor(f0, o, 64);
+    f1 += __shfl_xor(f1, o, 64);
+    f2 += __shfl_xor(f2, o, 64);
+  }
   const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
-  y[3 * n] = f0;
-  y[3 * n + 1] = f1;
-  y[3 * n + 2] = f2;
+  if (e < 3) y[3 * n + e] = e == 0 ? f0 : (e == 1 ? f1 : f2);
 }
 
 void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
@@ -630,7 +650,7 @@ void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, 
     k_apply_lattice<<<(int)nb, kTX * kTY * kTZ, 0, st>>>(M, x, y);
     const long long NX = M.lat[0] + 1, NY = M.lat[1] + 1, nz = M.lat[2];
     const long long nbnd = 2 * NX * NY + 2 * NX * (nz - 1) + 2 * (NY - 2) * (nz - 1);
-    k_apply_lattice_bnd<<<nblk(nbnd, 256), 256, 0, st>>>(M, x, y);
+    k_apply_lattice_bnd<<<nblk(8 * nbnd, 256), 256, 0, st>>>(M, x, y);
     return;
   }
   if (prec == 0 && M.model == kLinear && M.ke != nullptr) {
