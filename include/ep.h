@@ -63,10 +63,19 @@ typedef enum { EP_LINEAR = 0, EP_NH = 1, EP_YEOH = 2 } ep_model;
 
 /* Arithmetic of the operator apply (stiffness matvec).  The Krylov recurrence, error
  * estimate, Hessenberg exponential and state are FP64 in every mode.
- *   EP_PREC_F64       : matvec in FP64
- *   EP_PREC_MIXED_F32 : element kernels in FP32 with FP32 accumulation; converted at the
- *                       FP64 Krylov vector boundary. */
-typedef enum { EP_PREC_F64 = 0, EP_PREC_MIXED_F32 = 1 } ep_precision;
+ *   EP_PREC_F64        : matvec in FP64
+ *   EP_PREC_MIXED_F32  : element kernels in FP32 with FP32 accumulation; converted at the
+ *                        FP64 Krylov vector boundary.
+ *   EP_PREC_MIXED_BF16 : element tangents (the element matrices of the operator's H, Sec. 2.3
+ *                        with the secant split of App. A) formed once per projection with
+ *                        BF16 matrix-core products and FP32 accumulation, stored in BF16
+ *                        (1152 bytes per element); every apply computes K_e x_e in FP32 with
+ *                        FP32 accumulation.  Needs a congruent mesh (every element a
+ *                        translate of element 0; EP_ERR_ARG at ep_bind_workspace otherwise),
+ *                        must be set before ep_bind_workspace, not available for batches.
+ *                        BF16 keeps 8 significant bits: operator and trajectory errors are of
+ *                        order 1e-3 relative (measured values are stated with the tests). */
+typedef enum { EP_PREC_F64 = 0, EP_PREC_MIXED_F32 = 1, EP_PREC_MIXED_BF16 = 2 } ep_precision;
 
 /* ------------------------------------------------------------------ lifetime */
 

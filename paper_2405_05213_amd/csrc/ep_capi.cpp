@@ -55,8 +55,9 @@ struct Inst {
   size_t o_xyz, o_conn, o_incp, o_inc, o_geo, o_geo32, o_vdet, o_mih, o_mh, o_p0, o_p0bar, o_faces, o_fincp,
       o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y, o_ke,
       o_stencil,
-      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr;
+      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr, o_psi, o_kst;
   Mesh M{};
+  bool kst_rest = false;       // the stored tangents are those of the rest-state operator
   KWork W{};
   // stepping state (host mirror)
   double t = 0.0;
@@ -266,6 +267,8 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_wscr = L.take(8 * 2 * Lp);
   I.o_ke = L.take(8 * 24 * kKeLd);
   I.o_stencil = L.take(8 * 27 * 9);
+  I.o_psi = L.take(2 * (size_t)kPsiValues);
+  I.o_kst = L.take(c->cfg.prec == 2 ? 2 * kst_values((long long)ne) : 0);
 }
 
 static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
@@ -420,6 +423,15 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
       M.stencil = dptr<double>(c, I.o_stencil);
     }
   }
+  M.kst = nullptr;
+  I.kst_rest = false;
+  if (c->cfg.prec == 2) {
+    if (!M.congruent)
+      return fail(c, EP_ERR_ARG, "BF16 element tangents need a congruent mesh (every element a translate of element 0)");
+    launch_psi(M, dptr<uint16_t>(c, I.o_psi), st);
+    EP_HIP(c, hipGetLastError());
+    M.kst = dptr<uint16_t>(c, I.o_kst);
+  }
   KWork& W = I.W;
   W.V = dptr<double>(c, I.o_V);
   W.Wun = dptr<double>(c, I.o_Wun);
@@ -466,8 +478,22 @@ static OpArgs op_linear(double tau, double t_eval) {
   return op;
 }
 
+// EP_PREC_MIXED_BF16: the element tangents of the operator about to be applied, formed
+// before its projection (those of the rest-state operator are kept while they stay valid).
+static ep_status form_tangents(ep_ctx* c, Inst& I, const OpArgs& op) {
+  if (c->cfg.prec != 2) return EP_OK;
+  const bool rest = I.model == EP_LINEAR || op.nsets == 0;
+  if (rest && I.kst_rest) return EP_OK;
+  launch_form_tangent(I.M, op, dptr<uint16_t>(c, I.o_psi), dptr<uint16_t>(c, I.o_kst), &I.W.ctrl->err, c->stream);
+  EP_HIP(c, hipGetLastError());
+  I.kst_rest = rest;
+  return EP_OK;
+}
+
 static ep_status run_expv(ep_ctx* c, Inst& I, const OpArgs& op, int kind, const double* xin, double* xout, int mode,
                           int log_idx) {
+  ep_status s = form_tangents(c, I, op);
+  if (s != EP_OK) return s;
   ExpvArgs a{};
   a.M = I.M;
   a.W = I.W;
@@ -681,8 +707,14 @@ ep_status ep_get_orthogonalization(ep_ctx* c, int* mode) {
 
 ep_status ep_set_precision(ep_ctx* c, ep_precision p) {
   if (!c) return EP_ERR_ARG;
-  if (p != EP_PREC_F64 && p != EP_PREC_MIXED_F32) return fail(c, EP_ERR_ARG, "unknown precision");
+  if (p != EP_PREC_F64 && p != EP_PREC_MIXED_F32 && p != EP_PREC_MIXED_BF16)
+    return fail(c, EP_ERR_ARG, "unknown precision");
+  if (p == EP_PREC_MIXED_BF16 && c->batch)
+    return fail(c, EP_ERR_ARG, "batches take EP_PREC_F64 or EP_PREC_MIXED_F32");
+  if (p == EP_PREC_MIXED_BF16 && c->bound && c->one.M.kst == nullptr)
+    return fail(c, EP_ERR_ORDER, "EP_PREC_MIXED_BF16 must be set before ep_bind_workspace");
   c->cfg.prec = (int)p;
+  c->one.kst_rest = false;
   return EP_OK;
 }
 
@@ -699,6 +731,7 @@ ep_status ep_workspace_size(ep_ctx* c, size_t* bytes) {
   if (!c->batch && (!c->mesh_set || !c->material_set))
     return fail(c, EP_ERR_ORDER, "workspace size needs the mesh and the material");
   if (c->batch && c->insts.empty()) return fail(c, EP_ERR_ORDER, "batch has no instances");
+  if (c->batch && c->cfg.prec == 2) return fail(c, EP_ERR_ARG, "batches take EP_PREC_F64 or EP_PREC_MIXED_F32");
   if (!c->bound) {
     if (!c->batch && c->ortho_user == 1 && c->cfg.m_max > kMaxCwyM)
       return fail(c, EP_ERR_ARG, "compact-WY orthogonalisation needs m_max <= 64");
@@ -897,6 +930,8 @@ ep_status ep_apply_H(ep_ctx* c, const double* u_lin, const double* x, double* y)
   if (s != EP_OK) return s;
   if (!x || !y) return fail(c, EP_ERR_ARG, "null vector");
   Inst& I = c->one;
+  s = form_tangents(c, I, op_from(u_lin, 1.0, 0.0));
+  if (s != EP_OK) return s;
   launch_apply_H(I.M, op_from(u_lin, 1.0, 0.0), c->cfg.prec, x, y, I.W.F, I.W.F32, &I.W.ctrl->err, c->stream);
   EP_HIP(c, hipGetLastError());
   return EP_OK;   // enqueued; a sticky device error is reported by the next ep_sync
@@ -922,6 +957,8 @@ ep_status ep_apply_A(ep_ctx* c, const double* u_lin, double tau, double pscale, 
   EP_HIP(c, hipMemcpyAsync(kn, h2, 16, hipMemcpyHostToDevice, c->stream));
   M.knots = kn;
   M.n_knots = 1;
+  s = form_tangents(c, I, op_from(u_lin, tau, 0.0));
+  if (s != EP_OK) return s;
   launch_apply_A(M, op_from(u_lin, tau, 0.0), c->cfg.prec, x, y, I.W.F, I.W.F32, &I.W.ctrl->err, c->stream);
   EP_HIP(c, hipGetLastError());
   return ep_sync(c);
@@ -969,6 +1006,8 @@ ep_status ep_arnoldi(ep_ctx* c, const double* u_lin, double tau, double pscale, 
   a.out_mode = 2;
   a.log_idx = -1;
   EP_HIP(c, hipMemsetAsync(I.W.H, 0, 8 * (size_t)(c->cfg.m_max + 1) * c->cfg.m_max, c->stream));
+  s = form_tangents(c, I, a.op);
+  if (s != EP_OK) return s;
   EP_HIP(c, launch_expv(a, c->cfg.prec, c->stream));
   s = ep_sync(c);
   if (s != EP_OK) return s;
@@ -1005,6 +1044,8 @@ ep_status ep_expv(ep_ctx* c, const double* u_lin, double tau, double pscale, con
   a.x_out = y;
   a.out_mode = 2;
   a.log_idx = -1;
+  s = form_tangents(c, I, a.op);
+  if (s != EP_OK) return s;
   EP_HIP(c, launch_expv(a, c->cfg.prec, c->stream));
   s = ep_sync(c);
   if (s != EP_OK) return s;
@@ -1049,6 +1090,8 @@ ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G
   a.x_out = I.W.X;
   a.out_mode = 2;
   a.log_idx = -1;
+  s = form_tangents(c, I, a.op);
+  if (s != EP_OK) return s;
   static const int cand[] = {1, 2, 4, 8, 12, 16, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512};
   hipEvent_t e0, e1;
   EP_HIP(c, hipEventCreate(&e0));

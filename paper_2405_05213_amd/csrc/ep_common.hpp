@@ -17,8 +17,17 @@ constexpr int kMaxCwyM = 64;         // largest subspace of the compact-WY ortho
 constexpr int kRing = 8;
 constexpr int kKeLd = 25;            // row stride of the stored element stiffness             // rounds of all-reduce slots of a workgroup team
 
-// material ids (ep_model)
-constexpr int kLinear = 0, kNH = 1, kYeoh = 2;
+// stored BF16 element tangents (ep_tangent.hpp): Psi has 72 (q, j, l) columns padded to
+// 5 K-steps of 16; tangents are stored in groups of 8 elements of 9 x 64 x 8 values
+constexpr int kPsiK = 80;
+constexpr int kPsiSteps = kPsiK / 16;
+constexpr int kPsiValues = 4 * kPsiSteps * 64 * 4;
+constexpr int kKstGroup = 9 * 64 * 8;
+__host__ __device__ inline size_t kst_values(long long n_e) { return (size_t)((n_e + 7) / 8) * kKstGroup; }
+
+// material ids (ep_model); kStored selects the operator kernels that apply stored element
+// tangents (any material, formed beforehand)
+constexpr int kLinear = 0, kNH = 1, kYeoh = 2, kStored = 3;
 
 // sticky device error codes (match ep_status)
 constexpr int kErrKrylov = -4, kErrInverted = -5, kErrNonfinite = -6, kErrDevice = -8;
@@ -39,6 +48,8 @@ struct Mesh {
   int lat[3];                 // congruent lattice (node i + (nx+1)(j + (ny+1)k), VTK order):
                               // nx, ny, nz; zeros otherwise
   const double* stencil;      // lattice: the 27 3x3 blocks of an interior node's rows of K
+  const uint16_t* kst;        // BF16 element tangents of the current operator (groups of 8
+                              // elements, see ep_tangent.hpp), null unless that mode is bound
   const double* mih;          // M^{-1/2} per DOF (0 on clamped DOFs)
   const double* mh;           // M^{1/2}  per DOF (0 on clamped DOFs)
   const double* p0bar;        // M^{-1/2} P0 per DOF (0 on clamped DOFs)
@@ -62,7 +73,7 @@ struct OpArgs {
 struct KrylovCfg {
   double tol;
   int m_max, check_every, m_fixed, k_fixed, max_substeps;
-  int prec;                   // 0 FP64, 1 FP32 element kernels
+  int prec;                   // 0 FP64, 1 FP32 element kernels, 2 stored BF16 element tangents
   int ortho;                  // 0: one team reduction per projection (sequential MGS);
                               // 1: MGS in compact-WY form, one vector reduction per step
 };

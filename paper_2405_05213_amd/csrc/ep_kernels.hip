@@ -661,6 +661,9 @@ void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, 
   if (prec == 0) {
     elem_forces_t<double>(M, op, x, 1.0, 0, F, err, st);
     k_gather_H<double><<<nblk(M.n3, 256), 256, 0, st>>>(M, F, y);
+  } else if (prec == 2) {
+    launch_elem_forces_kst(M, x, 1.0, 0, F32, st);
+    k_gather_H<float><<<nblk(M.n3, 256), 256, 0, st>>>(M, F32, y);
   } else {
     elem_forces_t<float>(M, op, x, 1.0, 0, F32, err, st);
     k_gather_H<float><<<nblk(M.n3, 256), 256, 0, st>>>(M, F32, y);
@@ -672,6 +675,9 @@ void launch_apply_A(const Mesh& M, const OpArgs& op, int prec, const double* x, 
   if (prec == 0) {
     elem_forces_t<double>(M, op, x, 1.0, 1, F, err, st);
     k_gather_A<double><<<nblk(M.Lp, 256), 256, 0, st>>>(M, F, op.tau, op.t_eval, x, y);
+  } else if (prec == 2) {
+    launch_elem_forces_kst(M, x, 1.0, 1, F32, st);
+    k_gather_A<float><<<nblk(M.Lp, 256), 256, 0, st>>>(M, F32, op.tau, op.t_eval, x, y);
   } else {
     elem_forces_t<float>(M, op, x, 1.0, 1, F32, err, st);
     k_gather_A<float><<<nblk(M.Lp, 256), 256, 0, st>>>(M, F32, op.tau, op.t_eval, x, y);

@@ -29,6 +29,11 @@ void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, 
 void launch_apply_A(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
                     int* err, hipStream_t st);
 void launch_expm(int m, const double* H, double* E, double* scr, hipStream_t st);
+// stored BF16 element tangents (ep_tangent.hip)
+void launch_psi(const Mesh& M, uint16_t* psi, hipStream_t st);
+void launch_form_tangent(const Mesh& M, const OpArgs& op, const uint16_t* psi, uint16_t* kst, int* err,
+                         hipStream_t st);
+void launch_elem_forces_kst(const Mesh& M, const double* src, double sc, int scale_mih, float* F, hipStream_t st);
 int energy_blocks(const Mesh& M);
 int energy_vec_blocks(const Mesh& M);
 void launch_energy(const Mesh& M, const double* S, double t, double* pe, double* pv, double* out, hipStream_t st);

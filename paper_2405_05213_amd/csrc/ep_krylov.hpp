@@ -18,6 +18,7 @@
 
 #include "ep_device.hpp"
 #include "ep_expm.hpp"
+#include "ep_tangent.hpp"
 
 namespace ep {
 
@@ -88,22 +89,28 @@ template <typename T, int MODEL>
 __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, const double* src,
                                                          double hinv, T* F, int rank, int G, const T* ke) {
   bool okA = true;
-  if constexpr (MODEL == kLinear && sizeof(T) == 8) {
-    if (ke != nullptr) {
-      for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
-        elem_force_ke(M, e, src, hinv, (const double*)ke, (double*)F);
-      return true;
-    }
-  }
-  if (elem_lanes<T, MODEL>() == 8) {
-    // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
+  if constexpr (MODEL == kStored) {
+    // stored BF16 element tangents, 8 lanes per element (formed before the launch)
     for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
-      okA &= elem_force_qp<T, MODEL>(M, op, e, src, hinv, true, F);
+      elem_force_kst(M, e, src, hinv, true, (float*)F);
   } else {
-    for (int e = rank * blockDim.x + threadIdx.x; e < M.n_elems; e += G * blockDim.x) {
-      T fe[8][3];
-      okA &= elem_force<T, MODEL>(M, op, e, src, hinv, true, fe);
-      store_force(M, e, fe, F);
+    if constexpr (MODEL == kLinear && sizeof(T) == 8) {
+      if (ke != nullptr) {
+        for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
+          elem_force_ke(M, e, src, hinv, (const double*)ke, (double*)F);
+        return true;
+      }
+    }
+    if (elem_lanes<T, MODEL>() == 8) {
+      // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
+      for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
+        okA &= elem_force_qp<T, MODEL>(M, op, e, src, hinv, true, F);
+    } else {
+      for (int e = rank * blockDim.x + threadIdx.x; e < M.n_elems; e += G * blockDim.x) {
+        T fe[8][3];
+        okA &= elem_force<T, MODEL>(M, op, e, src, hinv, true, fe);
+        store_force(M, e, fe, F);
+      }
     }
   }
   return okA;
@@ -229,7 +236,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     // the next basis slice is loaded while each reduction is in flight
     // prefetch only in the linear kernels (reduction-latency bound); the secant-material
     // kernels need those registers for their element code
-    const bool pf_ok = (MODEL == kLinear) && nloc <= kPF * (int)blockDim.x;
+    const bool pf_ok = (MODEL == kLinear || MODEL == kStored) && nloc <= kPF * (int)blockDim.x;
     double pf[kPF];
     double hp = tm.post(part, red, flag, false);
     if (pf_ok && 1 < j) prefetch_row(pf, W.V + Lp + c0, nloc);

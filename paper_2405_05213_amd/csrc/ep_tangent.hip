@@ -1,0 +1,205 @@
+// Formation of the stored BF16 element tangents (see ep_tangent.hpp) and the stand-alone
+// operator apply that uses them.
+#include "ep_kernels.hpp"
+#include "ep_tangent.hpp"
+
+namespace ep {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Psi[(A,B), (q,j,l)] = dN_A/dX_j(q) dN_B/dX_l(q) of the congruent mesh (FP64, rounded to
+// BF16), zero in the padding columns 72..79, stored as the A operands of
+// v_mfma_f32_16x16x16_bf16: row tile w (rows 16 w .. 16 w + 15), K-step s, lane l holds
+// Psi[16 w + l % 16][16 s + 4 (l / 16) + v], v = 0..3.  One thread per value.
+__global__ void k_psi(Mesh M, uint16_t* __restrict__ psi) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= kPsiValues) return;
+  const int v = t & 3, l = (t >> 2) & 63, ws = t >> 8;
+  const int s = ws % kPsiSteps, w = ws / kPsiSteps;
+  const int r = 16 * w + (l & 15), kk = 16 * s + 4 * (l >> 4) + v;
+  double val = 0.0;
+  if (kk < 72) {
+    const int A = r >> 3, B = r & 7;
+    const int q = kk / 9, j = (kk % 9) / 3, jl = kk % 3;
+    const QFactors<double> Q(q);
+    const double* Ji = M.geo + (size_t)q * 10;
+    double gA = 0.0, gB = 0.0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      gA += Q.dN(A, m) * Ji[m * 3 + j];
+      gB += Q.dN(B, m) * Ji[m * 3 + jl];
+    }
+    val = gA * gB;
+  }
+  psi[t] = f32_to_bf16((float)val);
+}
+
+// One workgroup forms the tangents of kTanElems elements:
+//  1. lane (element el, Gauss point q) evaluates the secant coefficients of the operator's
+//     sets at q (FP32, inputs relative to node 0) and writes its 81 entries of C_q, times
+//     w det J, as BF16 into Cbar^T (LDS, row n = 9 el + 3 i + k, column 9 q + 3 j + l);
+//  2. wave w multiplies its row tile of Psi (A in {2w, 2w+1}) by all 18 column tiles of
+//     Cbar on the matrix cores (5 K-steps each, FP32 accumulation);
+//  3. the results, rounded to BF16, are staged in LDS in the stored layout and written out
+//     with 16-byte stores.
+template <int MODEL>
+__global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op, const uint16_t* __restrict__ psi,
+                                                             uint16_t* __restrict__ kst, int* err) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[9 * kTanElems * kTanLd];
+  const int el = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int e = blockIdx.x * kTanElems + el;
+  // ---- 1. C_q of this (element, point): coefficients of every set first, then the 81
+  //         entries row by row (few values live at once)
+  bool ok = true;
+  const int nsets = (MODEL == kLinear || e >= M.n_elems) ? 0 : op.nsets;
+  const float wdet = e < M.n_elems ? M.geo32[(size_t)q * 10 + 9] : 0.f;
+  Secant<float> sc[2] = {};          // zero coefficients for an absent set (weight 0)
+  float wsv[2] = {0.f, 0.f};
+  if (nsets > 0) {
+    const QFactors<float> Q(q);
+    float Jinv[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Jinv[k] = M.geo32[(size_t)q * 10 + k];
+    int nd[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s < nsets) {
+        float Du[3][3];
+        grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
+        ok &= secant_coeffs<float, MODEL>(Du, M.mp, sc[s]);
+        wsv[s] = float(op.wts[s]) * wdet;
+      }
+    }
+  }
+  if (!ok) atomicCAS(err, 0, kErrInverted);
+  float lam = 0.f, mu = 0.f;
+  if (nsets == 0 && e < M.n_elems) {
+    double lam_d, mu_d;
+    rest_lame(M.model, M.mp, lam_d, mu_d);
+    lam = float(lam_d) * wdet;
+    mu = float(mu_d) * wdet;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint16_t* row = lds + (size_t)(9 * el + 3 * i + k) * kTanLd + 9 * q;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          float c;
+          if (nsets == 0) {
+            c = ((i == k && j == l) ? mu : 0.f) + ((i == l && j == k) ? mu : 0.f) + ((i == j && k == l) ? lam : 0.f);
+          } else {
+            c = 0.f;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+              float t = sc[s].G[i][j] * sc[s].W[k][l];
+              if (i == k && j == l) t += sc[s].a;
+              if (j == k) t += sc[s].a * sc[s].G[i][l];
+              c += wsv[s] * t;          // wsv = 0 for an absent set
+            }
+          }
+          row[3 * j + l] = f32_to_bf16(c);
+        }
+    }
+  // zero K-padding (columns 72..79) of this lane's rows: lane q of element el clears row
+  // 9 el + q (and lane 0 also row 9 el + 8)
+  {
+    uint16_t* row = lds + (size_t)(9 * el + q) * kTanLd;
+#pragma unroll
+    for (int c = 72; c < kPsiK; ++c) row[c] = 0;
+    if (q == 0) {
+      uint16_t* r8 = lds + (size_t)(9 * el + 8) * kTanLd;
+#pragma unroll
+      for (int c = 72; c < kPsiK; ++c) r8[c] = 0;
+    }
+  }
+  __syncthreads();
+  // ---- 2. matrix-core products
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  bf16x4 af[kPsiSteps];
+  {
+    const uint2* pp = reinterpret_cast<const uint2*>(psi);
+#pragma unroll
+    for (int s = 0; s < kPsiSteps; ++s) {
+      const uint2 u = pp[(w * kPsiSteps + s) * 64 + lane];
+      af[s][0] = (short)(u.x & 0xffffu);
+      af[s][1] = (short)(u.x >> 16);
+      af[s][2] = (short)(u.y & 0xffffu);
+      af[s][3] = (short)(u.y >> 16);
+    }
+  }
+  constexpr int kCT = 9 * kTanElems / 16;          // 18 column tiles
+  f32x4 acc[kCT];
+#pragma unroll
+  for (int ct = 0; ct < kCT; ++ct) {
+    acc[ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* bro = lds + (size_t)(16 * ct + (lane & 15)) * kTanLd + 4 * (lane >> 4);
+#pragma unroll
+    for (int s = 0; s < kPsiSteps; ++s) {
+      const uint2 u = *reinterpret_cast<const uint2*>(bro + 16 * s);
+      bf16x4 bf;
+      bf[0] = (short)(u.x & 0xffffu);
+      bf[1] = (short)(u.x >> 16);
+      bf[2] = (short)(u.y & 0xffffu);
+      bf[3] = (short)(u.y >> 16);
+      acc[ct] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af[s], bf, acc[ct], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  // ---- 3. stage in the stored layout (lane l, item v: row 16 w + 4 (l / 16) + v, column
+  //         16 ct + l % 16), then write the workgroup's groups of 8 elements
+#pragma unroll
+  for (int ct = 0; ct < kCT; ++ct) {
+    const int n = 16 * ct + (lane & 15);
+    const int eo = n / 9, ik = n % 9;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * w + 4 * (lane >> 4) + v;
+      const int A = r >> 3, B = r & 7;
+      const int f = 9 * B + ik;
+      const int L = (eo & 7) * 8 + A;
+      lds[(size_t)(eo >> 3) * kKstGroup + ((f >> 3) * 64 + L) * 8 + (f & 7)] = f32_to_bf16(acc[ct][v]);
+    }
+  }
+  __syncthreads();
+  const long long groups = (M.n_elems + 7) / 8;
+  const long long g0 = (long long)blockIdx.x * (kTanElems / 8);
+  const int ng = (int)min<long long>(kTanElems / 8, groups - g0);
+  const uint4* src = reinterpret_cast<const uint4*>(lds);
+  uint4* dst = reinterpret_cast<uint4*>(kst) + (size_t)g0 * (kKstGroup / 8);
+  for (int t = threadIdx.x; t < ng * (kKstGroup / 8); t += blockDim.x) dst[t] = src[t];
+}
+
+// F = K_e x_e over all elements (stand-alone apply), 8 lanes per element
+__global__ __launch_bounds__(256) void k_elem_forces_kst(Mesh M, const double* __restrict__ src, double sc,
+                                                         int scale_mih, float* __restrict__ F) {
+  const int e = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 3);
+  if (e < M.n_elems) elem_force_kst(M, e, src, sc, scale_mih != 0, F);
+}
+
+void launch_psi(const Mesh& M, uint16_t* psi, hipStream_t st) {
+  k_psi<<<(kPsiValues + 255) / 256, 256, 0, st>>>(M, psi);
+}
+
+void launch_form_tangent(const Mesh& M, const OpArgs& op, const uint16_t* psi, uint16_t* kst, int* err,
+                         hipStream_t st) {
+  if (M.n_elems <= 0) return;
+  const int nb = (M.n_elems + kTanElems - 1) / kTanElems;
+  if (M.model == kLinear) k_form_tangent<kLinear><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
+  else if (M.model == kNH) k_form_tangent<kNH><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
+  else k_form_tangent<kYeoh><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
+}
+
+void launch_elem_forces_kst(const Mesh& M, const double* src, double sc, int scale_mih, float* F, hipStream_t st) {
+  if (M.n_elems <= 0) return;
+  const long long threads = (long long)M.n_elems * 8;
+  k_elem_forces_kst<<<(int)((threads + 255) / 256), 256, 0, st>>>(M, src, sc, scale_mih, F);
+}
+
+}  // namespace ep

@@ -115,3 +115,33 @@ def test_orthogonalization_modes():
     assert e.value.code == epmod.EP_ERR_ARG
     # the vector all-reduce slots make the compact-WY workspace larger
     assert ctx(64, 1).workspace_size() >= ctx(64, 0).workspace_size()
+
+
+def test_precision_modes():
+    """The BF16-tangent mode reserves its stored tangents (1152 bytes per element, groups of
+    8 elements) in the workspace; unknown modes are refused, and batches take only the FP64
+    and FP32 modes."""
+    p = config("c3", nx=9, ny=2, nz=2)
+
+    def size(prec):
+        c = _host_ctx()
+        c.set_mesh(p.xyz, p.conn)
+        c.set_material("nh", (0.4e6, 2e6), 1100.0)
+        c.set_precision(prec)
+        return c.workspace_size()
+
+    n_e = p.conn.shape[0]
+    assert size("mixed_f32") == size("f64")
+    assert size("mixed_bf16") - size("f64") >= 1152 * 8 * ((n_e + 7) // 8)
+    L = epmod.lib()
+    c = _host_ctx()
+    assert L.ep_set_precision(c.h, 3) == epmod.EP_ERR_ARG
+    b = epmod.Batch(device=-1)
+    b.set_precision("mixed_bf16")               # before the first instance: refused at sizing
+    b.add(config("c3", nx=20, ny=4, nz=4))
+    with pytest.raises(epmod.EPError) as e:
+        b.workspace_size()
+    assert e.value.code == epmod.EP_ERR_ARG
+    assert L.ep_set_precision(b.h, 2) == epmod.EP_ERR_ARG
+    assert L.ep_set_precision(b.h, 1) == epmod.EP_OK
+    assert b.workspace_size() > 0
