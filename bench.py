@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--dt", type=float, default=1e-4)
     ap.add_argument("--m-max", type=int, default=64)
-    ap.add_argument("--precision", default="f64", choices=["f64", "mixed_f32"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "mixed_f32", "mixed_bf16"])
     ap.add_argument("--workgroups", type=int, default=0)
     ap.add_argument("--ortho", type=int, default=-1, choices=[-1, 0, 1],
                     help="Gram-Schmidt form: -1 automatic, 0 sequential, 1 compact WY")
@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--tangents-only", action="store_true",
+                    help="only the BF16 tangent formation / apply on the 64^3 Yeoh block (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run 3 device copies of 256 MiB (counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -232,6 +234,71 @@ def run_matvec(prob, u_lin, reps, stream, torch, args):
                          "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_apply": alg}}
 
 
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def run_tangents(prob, u_lin, reps, stream, torch, args):
+    """BF16 element tangents: the formation alone (ep_form_tangents) and formation + apply
+    (ep_apply_H), each captured `reps` times in a graph and replayed.  Algorithmic work of a
+    formation: the shared-gradient product Psi (64 x 72) . Cbar (72 x 9) per element on the
+    matrix cores (2 * 64 * 72 * 9 flops); its algorithmic bytes: u (3 n_n doubles) and the
+    connectivity read, the tangents written (1152 B per element)."""
+    from paper_2405_05213_amd import solver_from_problem
+    side = torch.cuda.Stream()
+    ctx = solver_from_problem(prob, m_max=4, precision="mixed_bf16", stream=side.cuda_stream)
+    n3 = 3 * prob.n_nodes
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    x = torch.randn(n3, dtype=torch.float64, device="cuda", generator=gen)
+    y = torch.zeros_like(x)
+    u = torch.as_tensor(u_lin, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ctx.apply_H(u, x, y)
+    y_eager = y.clone()
+    out = {}
+    for what in ("form", "form_apply"):
+        y.zero_()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            for _ in range(reps):
+                if what == "form":
+                    ctx.form_tangents(u, sync=False)
+                else:
+                    ctx.apply_H(u, x, y, sync=False)
+        graph.replay()
+        side.synchronize()
+        if what == "form_apply":
+            out["graph_replay_matches"] = bool(torch.equal(y, y_eager))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(side):
+            e0.record(side)
+            for _ in range(5):
+                graph.replay()
+            e1.record(side)
+        side.synchronize()
+        out[f"us_per_{what}"] = e0.elapsed_time(e1) * 1e3 / (5 * reps)
+        del graph
+    ctx.sync()
+    us = out["us_per_form"]
+    flops = 2.0 * 64 * 72 * 9 * prob.n_elems
+    alg_bytes = n3 * 8 + 32 * prob.n_elems + 1152 * prob.n_elems
+    tf = flops / (us * 1e-6) / 1e12
+    gbs = alg_bytes / (us * 1e-6) / 1e9
+    log(args, f"  tangents {prob.name} {prob.grid}: form {us:.1f} us ({tf:.1f} TFLOP/s, {gbs:.0f} GB/s), "
+              f"form+apply {out['us_per_form_apply']:.1f} us")
+    out.update({
+        "elements": prob.n_elems,
+        "us_per_apply_estimate": out["us_per_form_apply"] - us,
+        "formation_mfma": {"bound": "hbm", "achieved_tflops": tf, "peak_tflops_bf16_dense": BF16_DENSE_PEAK_TFLOPS,
+                           "frac_mfma": tf / BF16_DENSE_PEAK_TFLOPS, "achieved_gbs": gbs, "peak_gbs": HBM_PEAK_GBS,
+                           "frac_hbm": gbs / HBM_PEAK_GBS, "flops_per_formation": flops,
+                           "alg_bytes_per_formation": alg_bytes},
+    })
+    del ctx
+    return out
+
+
 def run_batch(probs, precision, steps, m_max, stream, torch, args):
     from paper_2405_05213_amd import batch_from_problems
     b = batch_from_problems(probs, m_max=m_max, precision=precision, stream=stream.cuda_stream)
@@ -273,6 +340,11 @@ def main():
     prob = config(args.config, dt=args.dt)
     if args.copy_probe:
         copy_probe(torch)
+    if args.tangents_only:
+        cube = config("c4")
+        u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
+        print(json.dumps({"tangents_cube64_yeoh_bf16": run_tangents(cube, u_aff, 20, stream, torch, args)}))
+        return
 
     head = run_single(prob, args.precision, args.steps, args.warmup, args.m_max, args.workgroups,
                       args.adaptive, stream, torch, args)
@@ -291,7 +363,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "f64 (Krylov) / f32 (operator)",
+        "dtype": {"f64": "f64", "mixed_f32": "f64 (Krylov) / f32 (operator)",
+                  "mixed_bf16": "f64 (Krylov) / bf16 tangents, f32 apply"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": f"{args.config}: linear steel cantilever {prob.grid[0]}x{prob.grid[1]}x{prob.grid[2]} hex8, "
@@ -321,10 +394,24 @@ def main():
         del mixed
         for name, dt, steps in (("c3", 1e-4, 20), ("c4", 1e-3, 8)):
             p = config(name, dt=dt)
-            for prec in ("f64", "mixed_f32"):
+            ref_state = None
+            for prec in ("f64", "mixed_f32", "mixed_bf16"):
                 r = run_single(p, prec, steps, 3, 64, 0, True, stream, torch, args)
-                extra[f"{name}_{prec}"] = {k: v for k, v in r.items() if k not in ("ctx", "step_ms", "energy_rel_err")}
-                extra[f"{name}_{prec}"]["free_dofs"] = p.n_free
+                e = {k: v for k, v in r.items() if k not in ("ctx", "step_ms", "energy_rel_err")}
+                e["free_dofs"] = p.n_free
+                # time-varying load: error of the final state (warm-up + timed steps, same
+                # steps in every precision) against the FP64 run, which matches the oracle to 1e-8
+                _, u, v = r["ctx"].get_state()
+                en = r["ctx"].energy()
+                if ref_state is None:
+                    ref_state = (u, v, en)
+                else:
+                    ur, vr, er = ref_state
+                    e["state_rel_err_vs_f64"] = {
+                        "u": float(np.linalg.norm(u - ur) / np.linalg.norm(ur)),
+                        "v": float(np.linalg.norm(v - vr) / np.linalg.norm(vr)),
+                        "energy": abs((en[0] + en[1] - en[2]) - (er[0] + er[1] - er[2])) / (er[0] + er[1])}
+                extra[f"{name}_{prec}"] = e
                 del r
         import dataclasses
         cube = config("c4")
@@ -335,6 +422,7 @@ def main():
             del q
         u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
         extra["matvec_cube64_yeoh_f64"] = run_matvec(cube, u_aff, 20, stream, torch, args)
+        extra["tangents_cube64_yeoh_bf16"] = run_tangents(cube, u_aff, 20, stream, torch, args)
         probs = batch_instances(256, seed=5, dt=2.5e-5)
         for prec in ("f64", "mixed_f32"):
             extra[f"c5_batch_{prec}"] = run_batch(probs, prec, 30, 32, stream, torch, args)

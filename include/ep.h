@@ -216,6 +216,13 @@ ep_status ep_get_step_log(ep_ctx* ctx, int n, int32_t* m_corr, int32_t* m_pred,
  * runs as one node-by-node pass with the stored element stiffness. */
 ep_status ep_apply_H(ep_ctx* ctx, const double* u_lin_dev, const double* x_dev, double* y_dev);
 
+/* EP_PREC_MIXED_BF16 contexts: form the stored BF16 element tangents of H(u_lin) (u_lin_dev:
+ * 3*n_nodes doubles on the device, NULL = rest state), the H formation of the predictor and
+ * corrector operators (Sec. 4.2, App. A) as one stage, for checking and timing.  ep_apply_H
+ * and the stepping calls form the tangents they need themselves.  Enqueued without waiting;
+ * det F <= 0 is reported by the next ep_sync.  EP_ERR_ORDER in the other modes. */
+ep_status ep_form_tangents(ep_ctx* ctx, const double* u_lin_dev);
+
 /* y = tau * A x with A the augmented first-order matrix (Sec. 2.3) at load scale
  * `pscale`, u_lin as in ep_apply_H.  x_dev, y_dev: vectors of ep_vector_length() doubles
  * in the library's layout [ubar (3 n_nodes) | vbar (3 n_nodes) | s | padding]. */

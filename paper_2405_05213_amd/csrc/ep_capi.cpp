@@ -937,6 +937,15 @@ ep_status ep_apply_H(ep_ctx* c, const double* u_lin, const double* x, double* y)
   return EP_OK;   // enqueued; a sticky device error is reported by the next ep_sync
 }
 
+ep_status ep_form_tangents(ep_ctx* c, const double* u_lin) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (c->cfg.prec != 2) return fail(c, EP_ERR_ORDER, "ep_form_tangents needs EP_PREC_MIXED_BF16");
+  Inst& I = c->one;
+  I.kst_rest = false;          // always form
+  return form_tangents(c, I, op_from(u_lin, 1.0, 0.0));
+}
+
 ep_status ep_vector_length(ep_ctx* c, int64_t* len, int64_t* padded) {
   if (!c || !len || !padded) return EP_ERR_ARG;
   if (c->batch || !c->mesh_set) return fail(c, EP_ERR_ORDER, "needs a single-instance mesh");

@@ -9,7 +9,7 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Psi[(A,B), (q,j,l)] = dN_A/dX_j(q) dN_B/dX_l(q) of the congruent mesh (FP64, rounded to
-// BF16), zero in the padding columns 72..79, stored as the A operands of
+// BF16) at column 10 q + 3 j + l (column 10 q + 9 is zero padding), stored as the A operands of
 // v_mfma_f32_16x16x16_bf16: row tile w (rows 16 w .. 16 w + 15), K-step s, lane l holds
 // Psi[16 w + l % 16][16 s + 4 (l / 16) + v], v = 0..3.  One thread per value.
 __global__ void k_psi(Mesh M, uint16_t* __restrict__ psi) {
@@ -19,9 +19,9 @@ __global__ void k_psi(Mesh M, uint16_t* __restrict__ psi) {
   const int s = ws % kPsiSteps, w = ws / kPsiSteps;
   const int r = 16 * w + (l & 15), kk = 16 * s + 4 * (l >> 4) + v;
   double val = 0.0;
-  if (kk < 72) {
+  if (kk % 10 != 9) {
     const int A = r >> 3, B = r & 7;
-    const int q = kk / 9, j = (kk % 9) / 3, jl = kk % 3;
+    const int q = kk / 10, j = (kk % 10) / 3, jl = (kk % 10) % 3;
     const QFactors<double> Q(q);
     const double* Ji = M.geo + (size_t)q * 10;
     double gA = 0.0, gB = 0.0;
@@ -36,13 +36,16 @@ __global__ void k_psi(Mesh M, uint16_t* __restrict__ psi) {
 }
 
 // One workgroup forms the tangents of kTanElems elements:
-//  1. lane (element el, Gauss point q) evaluates the secant coefficients of the operator's
-//     sets at q (FP32, inputs relative to node 0) and writes its 81 entries of C_q, times
-//     w det J, as BF16 into Cbar^T (LDS, row n = 9 el + 3 i + k, column 9 q + 3 j + l);
+//  1. lane (element el, Gauss point q) loads node q of the element, obtains the others by
+//     shuffles, evaluates the secant coefficients of the operator's sets at q (FP32, inputs
+//     relative to node 0) and writes its 81 entries of C_q, times w det J, as BF16 into
+//     Cbar^T (LDS, row n = 9 el + 3 i + k, columns 10 q .. 10 q + 9: 3 j + l, then a zero),
+//     five 4-byte stores per row;
 //  2. wave w multiplies its row tile of Psi (A in {2w, 2w+1}) by all 18 column tiles of
 //     Cbar on the matrix cores (5 K-steps each, FP32 accumulation);
-//  3. the results, rounded to BF16, are staged in LDS in the stored layout and written out
-//     with 16-byte stores.
+//  3. the results, rounded to BF16, are staged in LDS in the stored layout (each lane's four
+//     accumulator rows are four consecutive B of one (A, i, k): one 8-byte store) and written
+//     out with 16-byte stores.
 template <int MODEL>
 __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op, const uint16_t* __restrict__ psi,
                                                              uint16_t* __restrict__ kst, int* err) {
@@ -56,19 +59,27 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
   const float wdet = e < M.n_elems ? M.geo32[(size_t)q * 10 + 9] : 0.f;
   Secant<float> sc[2] = {};          // zero coefficients for an absent set (weight 0)
   float wsv[2] = {0.f, 0.f};
-  if (nsets > 0) {
+  if (nsets > 0) {                 // uniform over the element's 8 lanes
     const QFactors<float> Q(q);
     float Jinv[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) Jinv[k] = M.geo32[(size_t)q * 10 + k];
-    int nd[8];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+    const int base = threadIdx.x & 63 & ~7;
+    const size_t dq = (size_t)M.conn[(size_t)e * 8 + q] * 3;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (s < nsets) {
+        const double* ul = op.ulin[s];
+        float ue[8][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const double v = ul[dq + i];
+          const float r = float(v - __shfl(v, base, 64));
+#pragma unroll
+          for (int a = 0; a < 8; ++a) ue[a][i] = __shfl(r, base + a, 64);
+        }
         float Du[3][3];
-        grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
+        grad_at(Q, ue, Jinv, Du);
         ok &= secant_coeffs<float, MODEL>(Du, M.mp, sc[s]);
         wsv[s] = float(op.wts[s]) * wdet;
       }
@@ -86,7 +97,8 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      uint16_t* row = lds + (size_t)(9 * el + 3 * i + k) * kTanLd + 9 * q;
+      uint16_t cv[10];
+      cv[9] = 0;
 #pragma unroll
       for (int j = 0; j < 3; ++j)
 #pragma unroll
@@ -104,21 +116,12 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
               c += wsv[s] * t;          // wsv = 0 for an absent set
             }
           }
-          row[3 * j + l] = f32_to_bf16(c);
+          cv[3 * j + l] = f32_to_bf16(c);
         }
-    }
-  // zero K-padding (columns 72..79) of this lane's rows: lane q of element el clears row
-  // 9 el + q (and lane 0 also row 9 el + 8)
-  {
-    uint16_t* row = lds + (size_t)(9 * el + q) * kTanLd;
+      uint32_t* row = reinterpret_cast<uint32_t*>(lds + (size_t)(9 * el + 3 * i + k) * kTanLd + 10 * q);
 #pragma unroll
-    for (int c = 72; c < kPsiK; ++c) row[c] = 0;
-    if (q == 0) {
-      uint16_t* r8 = lds + (size_t)(9 * el + 8) * kTanLd;
-#pragma unroll
-      for (int c = 72; c < kPsiK; ++c) r8[c] = 0;
+      for (int h = 0; h < 5; ++h) row[h] = (uint32_t)cv[2 * h] | ((uint32_t)cv[2 * h + 1] << 16);
     }
-  }
   __syncthreads();
   // ---- 2. matrix-core products
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -154,17 +157,17 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
   __syncthreads();
   // ---- 3. stage in the stored layout (lane l, item v: row 16 w + 4 (l / 16) + v, column
   //         16 ct + l % 16), then write the workgroup's groups of 8 elements
+  {
+    const int A = 2 * w + ((lane >> 4) >> 1), B0 = 4 * ((lane >> 4) & 1);   // rows 8 A + B0 + v
 #pragma unroll
-  for (int ct = 0; ct < kCT; ++ct) {
-    const int n = 16 * ct + (lane & 15);
-    const int eo = n / 9, ik = n % 9;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int r = 16 * w + 4 * (lane >> 4) + v;
-      const int A = r >> 3, B = r & 7;
-      const int f = 9 * B + ik;
+    for (int ct = 0; ct < kCT; ++ct) {
+      const int n = 16 * ct + (lane & 15);
+      const int eo = n / 9, ik = n % 9;
       const int L = (eo & 7) * 8 + A;
-      lds[(size_t)(eo >> 3) * kKstGroup + ((f >> 3) * 64 + L) * 8 + (f & 7)] = f32_to_bf16(acc[ct][v]);
+      uint2 pk;
+      pk.x = (uint32_t)f32_to_bf16(acc[ct][0]) | ((uint32_t)f32_to_bf16(acc[ct][1]) << 16);
+      pk.y = (uint32_t)f32_to_bf16(acc[ct][2]) | ((uint32_t)f32_to_bf16(acc[ct][3]) << 16);
+      *reinterpret_cast<uint2*>(lds + (size_t)(eo >> 3) * kKstGroup + (ik * 64 + L) * 8 + B0) = pk;
     }
   }
   __syncthreads();

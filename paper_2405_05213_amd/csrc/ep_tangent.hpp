@@ -9,14 +9,14 @@
 // gradients dN/dX are the same for every element, so all element matrices come from one
 // product with a shared left factor:
 //   K[(A,B), (i,k,e)] = Psi[(A,B), (q,j,l)] . Cbar[(q,j,l), (i,k,e)],
-//   Psi = dN_A/dX_j(q) dN_B/dX_l(q)   (64 x 72, padded to 80),
+//   Psi = dN_A/dX_j(q) dN_B/dX_l(q)   (64 x 80: column 10 q + 3 j + l, 10 q + 9 zero),
 // formed by k_form_tangent with BF16 matrix-core products and FP32 accumulation, and stored
 // rounded to BF16.  Every operator apply then reads K_e and computes K_e x_e in FP32.
 //
 // Storage: elements in groups of 8 (the 8 elements one wave applies); group g holds
-// 9 chunks x 64 lanes x 8 BF16 values; lane L = 8 (e mod 8) + A of chunk c holds
-// K_e[(A, .), .] at flat positions 8c .. 8c + 7 of the order f = 9 B + 3 i + k, so that each
-// of the nine 16-byte loads of a wave reads 1 KiB of contiguous memory.
+// 9 chunks x 64 lanes x 8 BF16 values; lane L = 8 (e mod 8) + A of chunk c = 3 i + k holds
+// K_e[(A, i), (B, k)] for B = 0..7, so that each of the nine 16-byte loads of a wave reads
+// 1 KiB of contiguous memory.
 #pragma once
 
 #include "ep_device.hpp"
@@ -67,11 +67,10 @@ __device__ __forceinline__ void elem_force_kst(const Mesh& M, int e, const doubl
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     const uint32_t w4[4] = {kv[c].x, kv[c].y, kv[c].z, kv[c].w};
+    const int i = c / 3, k = c % 3;
 #pragma unroll
-    for (int h = 0; h < 8; ++h) {
-      const int f = 8 * c + h;                     // 9 B + 3 i + k
-      const int B = f / 9, i = (f % 9) / 3, k = f % 3;
-      const uint32_t bits = (h & 1) ? (w4[h >> 1] >> 16) : (w4[h >> 1] & 0xffffu);
+    for (int B = 0; B < 8; ++B) {
+      const uint32_t bits = (B & 1) ? (w4[B >> 1] >> 16) : (w4[B >> 1] & 0xffffu);
       s[i] += bf16_to_f32(bits) * xe[3 * B + k];
     }
   }

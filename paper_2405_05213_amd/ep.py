@@ -58,6 +58,7 @@ _SIGS = {
     "ep_get_stats": [_vp, _P(_i64), _P(C.c_int), _P(_dbl), _P(C.c_int), _P(_dbl)],
     "ep_get_step_log": [_vp, C.c_int, _vp, _vp, _vp, _vp],
     "ep_apply_H": [_vp, _vp, _vp, _vp],
+    "ep_form_tangents": [_vp, _vp],
     "ep_apply_A": [_vp, _vp, _dbl, _dbl, _vp, _vp],
     "ep_vector_length": [_vp, _P(_i64), _P(_i64)],
     "ep_expm": [_vp, C.c_int, _vp, _vp],
@@ -248,6 +249,11 @@ class Context:
 
     def apply_H(self, u_lin, x, y, sync=True):
         self._call("ep_apply_H", _ptr(u_lin), _ptr(x), _ptr(y))
+        if sync:
+            self.sync()
+
+    def form_tangents(self, u_lin, sync=True):
+        self._call("ep_form_tangents", _ptr(u_lin))
         if sync:
             self.sync()
 

@@ -32,15 +32,19 @@ def summarize(db: str, top: int = 15):
 
 
 def counters(db: str, top: int = 15):
-    """Average value per dispatch of every collected counter, per kernel (rocprofv3 --pmc)."""
+    """Value per dispatch of every collected counter, per kernel (rocprofv3 --pmc): the
+    counter's rows of one dispatch (one per shader engine / instance for the basic SQ
+    counters) are summed, then averaged over the dispatches."""
     con = sqlite3.connect(db)
     rows = con.execute(
-        "select kernel_name, counter_name, count(distinct dispatch_id), avg(value), min(value), max(value) "
-        "from counters_collection group by kernel_name, counter_name order by avg(value) desc").fetchall()
-    out = [f"{'kernel':<70} {'counter':<14} {'dispatches':>10} {'avg':>16} {'min':>16} {'max':>16}"]
+        "select kernel_name, counter_name, count(*), avg(v), min(v), max(v) from "
+        "(select kernel_name, counter_name, dispatch_id, sum(value) as v from counters_collection "
+        " group by kernel_name, counter_name, dispatch_id) "
+        "group by kernel_name, counter_name order by avg(v) desc").fetchall()
+    out = [f"{'kernel':<70} {'counter':<28} {'dispatches':>10} {'avg':>16} {'min':>16} {'max':>16}"]
     for r in rows[: top * 4]:
         name = r[0] if len(r[0]) <= 70 else r[0][:67] + "..."
-        out.append(f"{name:<70} {r[1]:<14} {r[2]:>10d} {r[3]:>16.1f} {r[4]:>16.1f} {r[5]:>16.1f}")
+        out.append(f"{name:<70} {r[1]:<28} {r[2]:>10d} {r[3]:>16.1f} {r[4]:>16.1f} {r[5]:>16.1f}")
     return "\n".join(out)
 
 
