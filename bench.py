@@ -89,13 +89,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expv_c2_linear_f64_traffic.json
 
 
 def kernel_sources_sha256():
-    import glob
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2405_05213_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    from paper_2405_05213_amd.profsum import projection_kernel_sha256
+    return projection_kernel_sha256()
 
 
 def measured_traffic(config_name, precision, m, k, workgroups):

@@ -512,68 +512,91 @@ __global__ void k_stencil_blocks(const double* __restrict__ Ke, double* __restri
 
 void launch_stencil_blocks(const double* Ke, double* B, hipStream_t st) { k_stencil_blocks<<<1, 256, 0, st>>>(Ke, B); }
 
-// y = K x on a congruent lattice, interior nodes: a workgroup takes a TX x TY x TZ block of
-// nodes and stages x over the block and its one-node halo in LDS (one array per component);
-// each interior node applies the 27 blocks B_o, whose addresses are uniform (scalar loads).
-// Nodes on the lattice boundary are left to k_apply_lattice_bnd.
-constexpr int kTX = 16, kTY = 8, kTZ = 4;
-constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2, kHN = kHX * kHY * kHZ;
+// y = K x on a congruent lattice, interior nodes (0 < i < nx, 0 < j < ny, 0 < k < nz): a
+// workgroup takes a kLX x kLY x kLZ block of interior nodes and stages x over the block and
+// its one-node halo in LDS (one array per component; halo rows of kLX + 2 nodes are 3 (kLX + 2)
+// contiguous doubles in device memory, loaded by whole waves, every load issued before the
+// first LDS store).  Each thread applies the 27 blocks B_o to kLU consecutive nodes along x:
+// for each (j, k) offset it reads the kLU + 2 halo columns once and uses them for all kLU
+// nodes (40.5 LDS reads per node instead of 81, 243 FMAs per node).  The B_o addresses are
+// uniform (scalar loads).  Lattice boundary nodes are left to k_apply_lattice_bnd.
+constexpr int kLU = 2, kLX = 32, kLY = 8, kLZ = 4;
+constexpr int kLTX = kLX / kLU;
+constexpr int kLThreads = kLTX * kLY * kLZ;
+constexpr int kLHX = kLX + 2, kLHY = kLY + 2, kLHZ = kLZ + 2, kLHN = kLHX * kLHY * kLHZ;
 
-__global__ __launch_bounds__(kTX * kTY * kTZ) void k_apply_lattice(Mesh M, const double* __restrict__ x,
-                                                                 double* __restrict__ y) {
-  __shared__ double xs[3][kHN];
+__global__ __launch_bounds__(kLThreads) void k_apply_lattice(Mesh M, const double* __restrict__ x,
+                                                            double* __restrict__ y) {
+  __shared__ double xs[3][kLHN];
   const int nx = M.lat[0], ny = M.lat[1], nz = M.lat[2];
   const int NX = nx + 1, NY = ny + 1, NZ = nz + 1;
-  const int bx = (NX + kTX - 1) / kTX, by = (NY + kTY - 1) / kTY;
+  const int bx = (nx - 1 + kLX - 1) / kLX, by = (ny - 1 + kLY - 1) / kLY;
   const int blk = blockIdx.x;
-  const int i0 = (blk % bx) * kTX, j0 = ((blk / bx) % by) * kTY, k0 = (blk / (bx * by)) * kTZ;
-  // halo rows (hj, hk) of kHX nodes (3 kHX doubles, one wave per row): every load of the
-  // thread is issued before the first LDS store
-  constexpr int kRows = kHY * kHZ, kWaves = kTX * kTY * kTZ / 64, kPer = (kRows + kWaves - 1) / kWaves;
+  const int i0 = 1 + (blk % bx) * kLX, j0 = 1 + ((blk / bx) % by) * kLY, k0 = 1 + (blk / (bx * by)) * kLZ;
+  constexpr int kRows = kLHY * kLHZ, kRowD = 3 * kLHX, kWaves = kLThreads / 64;
+  constexpr int kPer = (kRows + kWaves - 1) / kWaves, kH = (kRowD + 63) / 64;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int hi = lane / 3, c = lane - 3 * (lane / 3);
-  const int gi = i0 - 1 + hi;
-  const bool oki = lane < 3 * kHX && gi >= 0 && gi < NX;
-  double v[kPer];
+  double v[kPer][kH];
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int row = wv + kWaves * r;
-    const int hj = row % kHY, hk = row / kHY;
-    const int gj = j0 - 1 + hj, gk = k0 - 1 + hk;
-    v[r] = 0.0;
-    if (row < kRows && oki && gj >= 0 && gj < NY && gk >= 0 && gk < NZ)
-      v[r] = x[((size_t)gi + (size_t)NX * ((size_t)gj + (size_t)NY * gk)) * 3 + c];
+    const int gj = j0 - 1 + row % kLHY, gk = k0 - 1 + row / kLHY;
+    const size_t base = ((size_t)(i0 - 1) + (size_t)NX * ((size_t)gj + (size_t)NY * gk)) * 3;
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+      const int t = lane + 64 * h;
+      const int gi = i0 - 1 + t / 3;
+      v[r][h] = (row < kRows && t < kRowD && gi < NX && gj < NY && gk < NZ) ? x[base + t] : 0.0;
+    }
   }
 #pragma unroll
   for (int r = 0; r < kPer; ++r) {
     const int row = wv + kWaves * r;
-    if (row < kRows && lane < 3 * kHX) xs[c][hi + kHX * row] = v[r];
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+      const int t = lane + 64 * h;
+      if (row < kRows && t < kRowD) xs[t % 3][t / 3 + kLHX * row] = v[r][h];
+    }
   }
   __syncthreads();
-  const int ti = threadIdx.x % kTX, tj = (threadIdx.x / kTX) % kTY, tk = threadIdx.x / (kTX * kTY);
-  const int i = i0 + ti, j = j0 + tj, k = k0 + tk;
-  if (!(i > 0 && i < nx && j > 0 && j < ny && k > 0 && k < nz)) return;
-  const int hc = (ti + 1) + kHX * ((tj + 1) + kHY * (tk + 1));
+  const int tx = threadIdx.x % kLTX, ty = (threadIdx.x / kLTX) % kLY, tz = threadIdx.x / (kLTX * kLY);
+  const int ib = i0 + kLU * tx, j = j0 + ty, k = k0 + tz;
+  if (ib >= nx || j >= ny || k >= nz) return;
   const double* __restrict__ B = M.stencil;
-  double f0 = 0.0, f1 = 0.0, f2 = 0.0;
+  double f[kLU][3];
 #pragma unroll
-  for (int o = 0; o < 27; ++o) {
-    const int h = hc + (o % 3 - 1) + kHX * ((o / 3) % 3 - 1) + kHX * kHY * (o / 9 - 1);
-    const double x0 = xs[0][h], x1 = xs[1][h], x2 = xs[2][h];
-    f0 = fma(B[9 * o + 0], x0, f0);
-    f1 = fma(B[9 * o + 3], x0, f1);
-    f2 = fma(B[9 * o + 6], x0, f2);
-    f0 = fma(B[9 * o + 1], x1, f0);
-    f1 = fma(B[9 * o + 4], x1, f1);
-    f2 = fma(B[9 * o + 7], x1, f2);
-    f0 = fma(B[9 * o + 2], x2, f0);
-    f1 = fma(B[9 * o + 5], x2, f1);
-    f2 = fma(B[9 * o + 8], x2, f2);
-  }
-  const size_t n = (size_t)i + (size_t)NX * ((size_t)j + (size_t)NY * k);
-  y[3 * n] = f0;
-  y[3 * n + 1] = f1;
-  y[3 * n + 2] = f2;
+  for (int u = 0; u < kLU; ++u) f[u][0] = f[u][1] = f[u][2] = 0.0;
+  // one (j, k) offset at a time: its 3 (kLU + 2) inputs stay in registers (unrolling the
+  // offsets lets the compiler hoist all 162 LDS reads and spend 256 VGPRs)
+#pragma unroll 1
+  for (int o9 = 0; o9 < 9; ++o9) {
+    const int dj = o9 % 3, dk = o9 / 3;
+      const int h0 = kLHX * ((ty + dj) + kLHY * (tz + dk)) + kLU * tx;
+      double xv[kLU + 2][3];
+#pragma unroll
+      for (int u = 0; u < kLU + 2; ++u)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xv[u][c] = xs[c][h0 + u];
+#pragma unroll
+      for (int di = 0; di < 3; ++di) {
+        const double* b = B + 9 * (di + 3 * dj + 9 * dk);
+#pragma unroll
+        for (int u = 0; u < kLU; ++u) {
+          const double x0 = xv[u + di][0], x1 = xv[u + di][1], x2 = xv[u + di][2];
+          f[u][0] = fma(b[0], x0, fma(b[1], x1, fma(b[2], x2, f[u][0])));
+          f[u][1] = fma(b[3], x0, fma(b[4], x1, fma(b[5], x2, f[u][1])));
+          f[u][2] = fma(b[6], x0, fma(b[7], x1, fma(b[8], x2, f[u][2])));
+        }
+      }
+    }
+  const size_t n0 = (size_t)ib + (size_t)NX * ((size_t)j + (size_t)NY * k);
+#pragma unroll
+  for (int u = 0; u < kLU; ++u)
+    if (ib + u < nx) {
+      y[3 * (n0 + u)] = f[u][0];
+      y[3 * (n0 + u) + 1] = f[u][1];
+      y[3 * (n0 + u) + 2] = f[u][2];
+    }
 }
 
 // Nodes on the lattice boundary: the faces k = 0, nz (all i, j), then j = 0, ny (0 < k < nz),
@@ -646,8 +669,11 @@ __global__ __launch_bounds__(256) void k_apply_lattice_bnd(Mesh M, const double*
 void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
                     int* err, hipStream_t st) {
   if (prec == 0 && M.model == kLinear && M.lat[0] > 0 && M.stencil != nullptr) {
-    const long long nb = (long long)((M.lat[0] + kTX) / kTX) * ((M.lat[1] + kTY) / kTY) * ((M.lat[2] + kTZ) / kTZ);
-    k_apply_lattice<<<(int)nb, kTX * kTY * kTZ, 0, st>>>(M, x, y);
+    if (M.lat[0] > 1 && M.lat[1] > 1 && M.lat[2] > 1) {
+      const long long nb = (long long)((M.lat[0] - 1 + kLX - 1) / kLX) * ((M.lat[1] - 1 + kLY - 1) / kLY) *
+                           ((M.lat[2] - 1 + kLZ - 1) / kLZ);
+      k_apply_lattice<<<(int)nb, kLThreads, 0, st>>>(M, x, y);
+    }
     const long long NX = M.lat[0] + 1, NY = M.lat[1] + 1, nz = M.lat[2];
     const long long nbnd = 2 * NX * NY + 2 * NX * (nz - 1) + 2 * (NY - 2) * (nz - 1);
     k_apply_lattice_bnd<<<nblk(8 * nbnd, 256), 256, 0, st>>>(M, x, y);

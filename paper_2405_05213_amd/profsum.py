@@ -48,13 +48,66 @@ def counters(db: str, top: int = 15):
     return "\n".join(out)
 
 
+# the sources that define the persistent projection kernel (the .hip files only instantiate it)
+PROJECTION_KERNEL_SOURCES = ("ep_common.hpp", "ep_device.hpp", "ep_expm.hpp", "ep_tangent.hpp", "ep_krylov.hpp",
+                             "ep_expv.hpp")
+
+
+def projection_kernel_sha256() -> str:
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in PROJECTION_KERNEL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _per_dispatch(db: str, counter: str, kernel_like: str):
+    con = sqlite3.connect(db)
+    return [r[1] for r in con.execute(
+        "select dispatch_id, sum(value) from counters_collection where counter_name = ? and kernel_name like ? "
+        "group by dispatch_id order by dispatch_id", (counter, kernel_like)).fetchall()]
+
+
+def traffic(fetch_db: str, write_db: str, kernel: str, last: int, bench_json: str, copy_kib: float = 262144.0):
+    """HBM bytes per launch of `kernel` from a FETCH_SIZE run and a WRITE_SIZE run of the same
+    command (KiB per dispatch, averaged over its last `last` dispatches), each scaled by what the
+    counter reads for the runtime's copy of copy_kib KiB (bench.py --copy-probe)."""
+    import json
+    f = _per_dispatch(fetch_db, "FETCH_SIZE", kernel)[-last:]
+    w = _per_dispatch(write_db, "WRITE_SIZE", kernel)[-last:]
+    cf = max(_per_dispatch(fetch_db, "FETCH_SIZE", "%copyBuffer%"))
+    cw = max(_per_dispatch(write_db, "WRITE_SIZE", "%copyBuffer%"))
+    fetch, write = sum(f) / len(f), sum(w) / len(w)
+    fs, ws = copy_kib / cf, copy_kib / cw
+    with open(bench_json) as fh:
+        b = json.loads(fh.read().strip().splitlines()[-1])
+    c = b["config"]
+    return {"kernel": kernel, "workload": c["workload"],
+            "dispatches": f"the {last} timed launches (last {last} dispatches of the kernel in each run)",
+            "fetch_kib_per_launch": fetch, "write_kib_per_launch": write, "copy_probe_kib": copy_kib,
+            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": fs, "write_scale": ws,
+            "traffic_bytes_per_launch": (fs * fetch + ws * write) * 1024.0,
+            "kernel_sources_sha256": projection_kernel_sha256(), "config": c["workload"].split(":")[0],
+            "precision": c["precision"], "m": c["m"], "k": c["substeps"], "workgroups": c["workgroups"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("db")
     ap.add_argument("--top", type=int, default=15)
     ap.add_argument("--counters", action="store_true", help="summarise PMC counters instead of durations")
+    ap.add_argument("--traffic", nargs=3, metavar=("WRITE_DB", "KERNEL", "BENCH_JSON"),
+                    help="db is the FETCH_SIZE run: print the per-launch traffic record of KERNEL")
+    ap.add_argument("--last", type=int, default=3)
     a = ap.parse_args()
-    print(counters(a.db, a.top) if a.counters else summarize(a.db, a.top))
+    if a.traffic:
+        import json
+        print(json.dumps(traffic(a.db, a.traffic[0], a.traffic[1], a.last, a.traffic[2]), indent=1))
+    else:
+        print(counters(a.db, a.top) if a.counters else summarize(a.db, a.top))
 
 
 if __name__ == "__main__":

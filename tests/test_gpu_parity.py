@@ -25,6 +25,8 @@ CASES_H = [
     ("linear", "c1", {}, True),
     ("linear", "c1", {}, "renumbered"),
     ("linear", "c1", dict(nx=19, ny=9, nz=5), False),
+    ("linear", "bar", dict(nx=16), False),                 # lattice with no interior nodes
+    ("linear", "c1", dict(nx=33, ny=9, nz=6), False),      # interior tiles cut in x, y and z
     ("nh", "c3", dict(nx=8, ny=2, nz=2), False),
     ("nh", "c3", dict(nx=8, ny=2, nz=2), True),
     ("yeoh", "c4", dict(nx=4, ny=3, nz=3), True),
