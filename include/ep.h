@@ -55,11 +55,15 @@ typedef enum {
  *               psi = mu/2 (I1 - 3) - mu ln J + lambda/2 (ln J)^2
  *   EP_YEOH   : {C10, C20, C30, D1}          Yeoh, psi = sum_k Ck0 (I1bar - 3)^k + (J-1)^2 / D1;
  *               C20 = C30 = 0 is the decoupled Neo-Hookean solid (mu = 2 C10, kappa = 2/D1)
+ *   EP_SVK    : {lambda, mu}                 St. Venant-Kirchhoff, S = lambda tr(E) I + 2 mu E,
+ *               E = (F^T F - I) / 2, psi = lambda/2 (tr E)^2 + mu E : E
  * For EP_NH and EP_YEOH, H(u) is the secant operator with H(u) u = R(u) exactly,
  *   (H(u) x)_A = sum_e sum_q w detJ [a (X + G X^T) + (W : X) G] . grad N_A,
  *   X = grad x, G = F^{-T}, with a, W scalar / matrix coefficients of grad u built as in
- *   App. A (det F - 1 = P_e : grad u; I1 - 3 = (2 I + grad u) : grad u). */
-typedef enum { EP_LINEAR = 0, EP_NH = 1, EP_YEOH = 2 } ep_model;
+ *   App. A (det F - 1 = P_e : grad u; I1 - 3 = (2 I + grad u) : grad u).  For EP_SVK the
+ *   secant stress is lambda ((I + grad u / 2) : X) F + mu F (X + X^T F) (its value at X = grad u
+ *   is P = F S). */
+typedef enum { EP_LINEAR = 0, EP_NH = 1, EP_YEOH = 2, EP_SVK = 3 } ep_model;
 
 /* Arithmetic of the operator apply (stiffness matvec).  The Krylov recurrence, error
  * estimate, Hessenberg exponential and state are FP64 in every mode.

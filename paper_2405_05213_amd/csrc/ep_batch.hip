@@ -144,10 +144,12 @@ static const void* batch_kernel(int prec, int model) {
   if (prec == 0) {
     if (model == kLinear) return reinterpret_cast<const void*>(&k_batch<double, kLinear>);
     if (model == kNH) return reinterpret_cast<const void*>(&k_batch<double, kNH>);
+    if (model == kSVK) return reinterpret_cast<const void*>(&k_batch<double, kSVK>);
     return reinterpret_cast<const void*>(&k_batch<double, kYeoh>);
   }
   if (model == kLinear) return reinterpret_cast<const void*>(&k_batch<float, kLinear>);
   if (model == kNH) return reinterpret_cast<const void*>(&k_batch<float, kNH>);
+  if (model == kSVK) return reinterpret_cast<const void*>(&k_batch<float, kSVK>);
   return reinterpret_cast<const void*>(&k_batch<float, kYeoh>);
 }
 

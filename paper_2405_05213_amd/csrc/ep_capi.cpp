@@ -88,8 +88,8 @@ struct ep_ctx {
   size_t o_batch_tab = 0;
   // batch
   std::vector<BatchInst> btab;          // host mirror of the device records
-  std::vector<int> bids[3];             // instance ids per material model
-  size_t o_bids[3] = {0, 0, 0};
+  std::vector<int> bids[kModels];       // instance ids per material model
+  size_t o_bids[kModels] = {};
   int max_lds_chunk = 0;
   hipGraphExec_t bgraph = nullptr;
   hipGraph_t bgraph_src = nullptr;
@@ -138,6 +138,9 @@ static ep_status check_material(ep_ctx* c, int model, const double* p, int n, do
   } else if (model == EP_YEOH) {
     if (n != 4) return fail(c, EP_ERR_ARG, "EP_YEOH takes {C10, C20, C30, D1}");
     if (!(p[0] > 0.0) || !(p[3] > 0.0)) return fail(c, EP_ERR_ARG, "need C10 > 0 and D1 > 0");
+  } else if (model == EP_SVK) {
+    if (n != 2) return fail(c, EP_ERR_ARG, "EP_SVK takes {lambda, mu}");
+    if (!(p[1] > 0.0) || !(p[0] >= 0.0)) return fail(c, EP_ERR_ARG, "need mu > 0 and lambda >= 0");
   } else {
     return fail(c, EP_ERR_ARG, "unknown material model");
   }
@@ -281,7 +284,7 @@ static size_t plan_all(ep_ctx* c) {
   } else {
     for (auto& I : c->insts) plan_inst(c, I, L, 1);
     c->o_batch_tab = L.take(sizeof(BatchInst) * std::max<size_t>(c->insts.size(), 1));
-    for (int k = 0; k < 3; ++k) c->o_bids[k] = L.take(4 * std::max<size_t>(c->insts.size(), 1));
+    for (int k = 0; k < kModels; ++k) c->o_bids[k] = L.take(4 * std::max<size_t>(c->insts.size(), 1));
   }
   return L.off + kAlign;
 }
@@ -1183,7 +1186,7 @@ ep_status ep_batch_bind(ep_ctx* c) {
   const int n = (int)c->insts.size();
   c->btab.assign(n, BatchInst{});
   c->max_lds_chunk = 0;
-  for (int k = 0; k < 3; ++k) c->bids[k].clear();
+  for (int k = 0; k < kModels; ++k) c->bids[k].clear();
   for (int i = 0; i < n; ++i) {
     Inst& I = c->insts[i];
     ep_status s = setup_inst(c, I, 1, I.Lp, 1);
@@ -1202,7 +1205,7 @@ ep_status ep_batch_bind(ep_ctx* c) {
     c->bids[I.model].push_back(i);
   }
   EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_batch_tab), c->btab.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice));
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < kModels; ++k)
     if (!c->bids[k].empty())
       EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_bids[k]), c->bids[k].data(), 4 * c->bids[k].size(),
                           hipMemcpyHostToDevice));
@@ -1251,7 +1254,7 @@ ep_status ep_batch_set_state(ep_ctx* c, int32_t id, double t, const double* u, c
 }
 
 static ep_status batch_launch_all(ep_ctx* c, double dt, int n_steps, hipStream_t st) {
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kModels; ++k) {
     if (c->bids[k].empty()) continue;
     EP_HIP(c, launch_batch(dptr<BatchInst>(c, c->o_batch_tab), dptr<int>(c, c->o_bids[k]), (int)c->bids[k].size(),
                            k, c->cfg, dt, n_steps, c->max_lds_chunk, st));

@@ -27,7 +27,8 @@ __host__ __device__ inline size_t kst_values(long long n_e) { return (size_t)((n
 
 // material ids (ep_model); kStored selects the operator kernels that apply stored element
 // tangents (any material, formed beforehand)
-constexpr int kLinear = 0, kNH = 1, kYeoh = 2, kStored = 3;
+constexpr int kLinear = 0, kNH = 1, kYeoh = 2, kSVK = 3, kStored = 4;
+constexpr int kModels = 4;
 
 // sticky device error codes (match ep_status)
 constexpr int kErrKrylov = -4, kErrInverted = -5, kErrNonfinite = -6, kErrDevice = -8;
@@ -57,7 +58,8 @@ struct Mesh {
   const double* knots;        // [2*n_knots]: times then scales
   int n_knots;
   int model;
-  double mp[4];               // linear (E, nu) | nh (mu, lambda) | yeoh (C10, C20, C30, D1)
+  double mp[4];               // linear (E, nu) | nh (mu, lambda) | yeoh (C10, C20, C30, D1) |
+                              // svk (lambda, mu)
   double s0, s_inv;           // augmented entry value and 1/s0 (0 when s0 == 0)
 };
 

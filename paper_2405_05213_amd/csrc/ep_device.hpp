@@ -193,6 +193,50 @@ __device__ __forceinline__ void secant_apply(const Secant<T>& s, T w, const T (&
     }
 }
 
+// St. Venant-Kirchhoff (App. A): S = lambda tr(E) I + 2 mu E with E = (F^T F - I) / 2.  The
+// first Piola-Kirchhoff stress P = F S written linearly in X = grad x:
+//   secant(D, X) = lambda ((I + D/2) : X) F + mu F (X + X^T F),
+// since (I + D/2) : D = tr E and D + D^T F = 2 E, so secant(D, D) = P and H(u) u = R(u).
+// The set keeps F and I + D/2.
+template <typename T>
+struct SecantSVK {
+  T F[3][3];
+  T Hh[3][3];
+};
+
+template <typename T>
+__device__ __forceinline__ void svk_coeffs(const T (&D)[3][3], SecantSVK<T>& s) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.F[i][k] = D[i][k] + (i == k ? T(1) : T(0));
+      s.Hh[i][k] = T(0.5) * D[i][k] + (i == k ? T(1) : T(0));
+    }
+}
+
+// S += w * [lambda (Hh : X) F + mu F (X + X^T F)]
+template <typename T>
+__device__ __forceinline__ void svk_apply(const SecantSVK<T>& s, T lam, T mu, T w, const T (&X)[3][3],
+                                          T (&S)[3][3]) {
+  T c = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c += s.Hh[i][k] * X[i][k];
+  T Y[3][3];   // X + X^T F
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Y[i][k] = X[i][k] + X[0][i] * s.F[0][k] + X[1][i] * s.F[1][k] + X[2][i] * s.F[2][k];
+  const T lc = w * lam * c, wm = w * mu;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      S[i][k] += lc * s.F[i][k] + wm * (s.F[i][0] * Y[0][k] + s.F[i][1] * Y[1][k] + s.F[i][2] * Y[2][k]);
+}
+
 // Lame constants of the linear material (E, nu) or of the rest-state tangent.
 __device__ __forceinline__ void rest_lame(int model, const double* mp, double& lam, double& mu) {
   if (model == kLinear) {
@@ -202,6 +246,9 @@ __device__ __forceinline__ void rest_lame(int model, const double* mp, double& l
   } else if (model == kNH) {
     mu = mp[0];
     lam = mp[1];
+  } else if (model == kSVK) {
+    lam = mp[0];
+    mu = mp[1];
   } else {
     mu = 2.0 * mp[0];
     lam = 2.0 / mp[3] - 2.0 * mu / 3.0;
@@ -285,7 +332,18 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) S[i][k] = T(0);
-      if (MODEL != kLinear) {
+      if constexpr (MODEL == kSVK) {
+        T Du[3][3];
+        SecantSVK<T> sv;
+        grad_at(Q, u0, Jinv, Du);
+        svk_coeffs(Du, sv);
+        svk_apply(sv, lam, mu, T(op.wts[0]), X, S);
+        if (nsets >= 2) {
+          grad_at(Q, u1, Jinv, Du);
+          svk_coeffs(Du, sv);
+          svk_apply(sv, lam, mu, T(op.wts[1]), X, S);
+        }
+      } else if (MODEL != kLinear) {
         T Du[3][3];
         Secant<T> sc;
         grad_at(Q, u0, Jinv, Du);
@@ -389,7 +447,17 @@ __device__ __forceinline__ bool elem_force_qp(const Mesh& M, const OpArgs& op, i
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int k = 0; k < 3; ++k) S[i][k] = T(0);
-    if (MODEL != kLinear) {
+    if constexpr (MODEL == kSVK) {
+      double lam_d, mu_d;
+      rest_lame(kSVK, M.mp, lam_d, mu_d);
+      for (int s = 0; s < nsets; ++s) {
+        T Du[3][3];
+        SecantSVK<T> sv;
+        grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
+        svk_coeffs(Du, sv);
+        svk_apply(sv, T(lam_d), T(mu_d), T(op.wts[s]), X, S);
+      }
+    } else if (MODEL != kLinear) {
       for (int s = 0; s < nsets; ++s) {
         T Du[3][3];
         Secant<T> sc;

@@ -73,11 +73,13 @@ inline const void* expv_kernel_sg(int prec, int model, int ortho) {
   if (prec == 0) {
     if (model == kLinear) return expv_fn<double, kLinear, SG>(ortho);
     if (model == kNH) return expv_fn<double, kNH, SG>(ortho);
+    if (model == kSVK) return expv_fn<double, kSVK, SG>(ortho);
     return expv_fn<double, kYeoh, SG>(ortho);
   }
   if (prec == 2) return expv_fn<float, kStored, SG>(ortho);
   if (model == kLinear) return expv_fn<float, kLinear, SG>(ortho);
   if (model == kNH) return expv_fn<float, kNH, SG>(ortho);
+  if (model == kSVK) return expv_fn<float, kSVK, SG>(ortho);
   return expv_fn<float, kYeoh, SG>(ortho);
 }
 

@@ -278,6 +278,17 @@ __global__ __launch_bounds__(kThreads) void k_expm(int m, const double* __restri
 // ---------------------------------------------------------------------------------------
 template <int MODEL>
 __device__ double psi_at(const double (&D)[3][3], const double* mp) {
+  if (MODEL == kSVK) {
+    // lambda/2 (tr E)^2 + mu E : E, E = (D + D^T + D^T D) / 2
+    double E[3][3], tr = 0.0, ee = 0.0;
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        E[i][k] = 0.5 * (D[i][k] + D[k][i] + D[0][i] * D[0][k] + D[1][i] * D[1][k] + D[2][i] * D[2][k]);
+        ee += E[i][k] * E[i][k];
+      }
+    tr = E[0][0] + E[1][1] + E[2][2];
+    return 0.5 * mp[0] * tr * tr + mp[1] * ee;
+  }
   if (MODEL == kLinear) {
     double lam, mu;
     rest_lame(kLinear, mp, lam, mu);
@@ -470,6 +481,7 @@ static void elem_forces_t(const Mesh& M, const OpArgs& op, const double* src, do
   if (M.n_elems == 0) return;
   if (M.model == kLinear) k_elem_forces<T, kLinear><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
   else if (M.model == kNH) k_elem_forces<T, kNH><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+  else if (M.model == kSVK) k_elem_forces<T, kSVK><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
   else k_elem_forces<T, kYeoh><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
 }
 
@@ -730,6 +742,7 @@ void launch_energy(const Mesh& M, const double* S, double t, double* pe, double*
   if (ne > 0) {
     if (M.model == kLinear) k_energy_elem<kLinear><<<ne, 256, 0, st>>>(M, S, pe);
     else if (M.model == kNH) k_energy_elem<kNH><<<ne, 256, 0, st>>>(M, S, pe);
+    else if (M.model == kSVK) k_energy_elem<kSVK><<<ne, 256, 0, st>>>(M, S, pe);
     else k_energy_elem<kYeoh><<<ne, 256, 0, st>>>(M, S, pe);
   }
   if (nv > 0) k_energy_vec<<<nv, 256, 0, st>>>(M.n3, S, M.p0bar, pv);

@@ -80,19 +80,33 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
         }
         float Du[3][3];
         grad_at(Q, ue, Jinv, Du);
-        ok &= secant_coeffs<float, MODEL>(Du, M.mp, sc[s]);
+        if constexpr (MODEL == kSVK) {
+          // St. Venant-Kirchhoff: F in G, I + D/2 in W
+          SecantSVK<float> sv;
+          svk_coeffs(Du, sv);
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              sc[s].G[a][b] = sv.F[a][b];
+              sc[s].W[a][b] = sv.Hh[a][b];
+            }
+        } else {
+          ok &= secant_coeffs<float, MODEL>(Du, M.mp, sc[s]);
+        }
         wsv[s] = float(op.wts[s]) * wdet;
       }
     }
   }
   if (!ok) atomicCAS(err, 0, kErrInverted);
-  float lam = 0.f, mu = 0.f;
-  if (nsets == 0 && e < M.n_elems) {
+  float lam_u = 0.f, mu_u = 0.f;   // rest-state (linear) / St. Venant-Kirchhoff moduli
+  if (e < M.n_elems) {
     double lam_d, mu_d;
     rest_lame(M.model, M.mp, lam_d, mu_d);
-    lam = float(lam_d) * wdet;
-    mu = float(mu_d) * wdet;
+    lam_u = float(lam_d);
+    mu_u = float(mu_d);
   }
+  const float lam = lam_u * wdet, mu = mu_u * wdet;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -110,9 +124,16 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
             c = 0.f;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
-              float t = sc[s].G[i][j] * sc[s].W[k][l];
-              if (i == k && j == l) t += sc[s].a;
-              if (j == k) t += sc[s].a * sc[s].G[i][l];
+              float t;
+              if constexpr (MODEL == kSVK) {
+                // d/dX_kl of lambda (Hh : X) F + mu (F X + F X^T F), unscaled by w det J
+                t = lam_u * sc[s].G[i][j] * sc[s].W[k][l] +
+                    mu_u * ((j == l ? sc[s].G[i][k] : 0.f) + sc[s].G[i][l] * sc[s].G[k][j]);
+              } else {
+                t = sc[s].G[i][j] * sc[s].W[k][l];
+                if (i == k && j == l) t += sc[s].a;
+                if (j == k) t += sc[s].a * sc[s].G[i][l];
+              }
               c += wsv[s] * t;          // wsv = 0 for an absent set
             }
           }
@@ -196,6 +217,7 @@ void launch_form_tangent(const Mesh& M, const OpArgs& op, const uint16_t* psi, u
   const int nb = (M.n_elems + kTanElems - 1) / kTanElems;
   if (M.model == kLinear) k_form_tangent<kLinear><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
   else if (M.model == kNH) k_form_tangent<kNH><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
+  else if (M.model == kSVK) k_form_tangent<kSVK><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
   else k_form_tangent<kYeoh><<<nb, kTanThreads, 0, st>>>(M, op, psi, kst, err);
 }
 

@@ -38,5 +38,12 @@ def from_gpu_vec(orc, x):
     return np.concatenate([x[orc.free], x[n3 + orc.free], [x[2 * n3]]])
 
 
+def svk_of(prob):
+    """The same problem with a St. Venant-Kirchhoff solid of the compressible Neo-Hookean
+    workload's Lame constants (lambda 2 MPa, mu 0.4 MPa): App. A's model family on the
+    Neo-Hookean cantilever shapes."""
+    return prob.with_(name=prob.name + "-svk", model="svk", params=(2.0e6, 0.4e6))
+
+
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))

@@ -5,7 +5,7 @@ import pytest
 
 from workloads import batch_instances, config
 from oracle.stepper import Propagator
-from tests.gpu_util import rel, say
+from tests.gpu_util import rel, say, svk_of
 
 pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -15,6 +15,7 @@ def _mixed_batch():
     probs = batch_instances(n_inst=3, seed=5, dt=2e-4, nx_range=(4, 8), nyz_range=(2, 3))
     probs.append(config("c1", dt=1e-4))
     probs.append(config("c4", nx=3, ny=3, nz=3, dt=2e-3))
+    probs.append(svk_of(config("c3", nx=6, ny=2, nz=2, dt=2e-4)))
     # slices of this one exceed the LDS budget: exercises the device-memory slice buffers
     big = batch_instances(n_inst=1, seed=9, dt=2e-4, nx_range=(40, 40), nyz_range=(8, 8))[0]
     probs.append(big)

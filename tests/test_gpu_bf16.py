@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from workloads import config, distort
-from tests.gpu_util import pair, rel, say
+from tests.gpu_util import pair, rel, say, svk_of
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -28,7 +28,8 @@ def _t(x):
 # group of 8 (its elements are smaller, hence the smaller random displacement that keeps
 # det F > 0)
 CASES = [("linear", "c1", {}, 0.0), ("nh", "c3", dict(nx=8, ny=2, nz=2), 0.03),
-         ("nh", "c3", dict(nx=19, ny=3, nz=2), 0.01), ("yeoh", "c4", dict(nx=4, ny=3, nz=3), 0.03)]
+         ("nh", "c3", dict(nx=19, ny=3, nz=2), 0.01), ("yeoh", "c4", dict(nx=4, ny=3, nz=3), 0.03),
+         ("svk", "c3", dict(nx=8, ny=2, nz=2), 0.03)]
 
 
 @pytest.mark.parametrize("model,name,over,amp", CASES)
@@ -36,6 +37,8 @@ def test_apply_H_bf16(model, name, over, amp):
     """y = H(u) x from the stored tangents at a deformed state (rest state for linear)."""
     say(f"[bf16 apply_H] {model} {name} {over}")
     p = config(name, **over)
+    if model == "svk":
+        p = svk_of(p)
     ctx, orc = pair(p, precision="mixed_bf16")
     rng = np.random.default_rng(3)
     n3 = 3 * p.n_nodes

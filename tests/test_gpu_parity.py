@@ -4,7 +4,7 @@ import pytest
 
 from workloads import config, distort
 from oracle import krylov
-from tests.gpu_util import from_gpu_vec, pair, rel, say, to_gpu_vec
+from tests.gpu_util import from_gpu_vec, pair, rel, say, svk_of, to_gpu_vec
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,6 +30,8 @@ CASES_H = [
     ("nh", "c3", dict(nx=8, ny=2, nz=2), False),
     ("nh", "c3", dict(nx=8, ny=2, nz=2), True),
     ("yeoh", "c4", dict(nx=4, ny=3, nz=3), True),
+    ("svk", "c3", dict(nx=8, ny=2, nz=2), False),
+    ("svk", "c3", dict(nx=8, ny=2, nz=2), True),
 ]
 
 
@@ -39,6 +41,8 @@ def test_apply_H_matches_oracle(model, name, over, distorted, prec):
     """Operator apply (weak-form term 2 with the secant split): y = H(u) x on all DOFs."""
     say(f"[apply_H] {model} {name} {over} distorted={distorted} prec={prec}")
     p = config(name, **over)
+    if model == "svk":
+        p = svk_of(p)
     if distorted == "renumbered":
         p = renumbered(p)
     elif distorted:
@@ -142,13 +146,17 @@ def test_linear_steps_c1(mode, ortho):
 
 
 @pytest.mark.parametrize("model,name,over", [("nh", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4)),
-                                              ("yeoh", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3))])
+                                              ("yeoh", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3)),
+                                              ("svk", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4))])
 @pytest.mark.parametrize("mode", ["fixed", "adaptive"])
 @pytest.mark.parametrize("ortho", [0, 1])
 def test_nonlinear_steps(model, name, over, mode, ortho):
-    """Predictor-corrector steps of the Neo-Hookean / Yeoh solids against the oracle."""
+    """Predictor-corrector steps of the Neo-Hookean / Yeoh / St. Venant-Kirchhoff solids
+    against the oracle."""
     say(f"[steps] {model} {name} {over} {mode} ortho={ortho}")
     p = config(name, **over)
+    if model == "svk":
+        p = svk_of(p)
     n = 12
     kw = dict(m_max=48) if mode == "adaptive" else dict(m_max=48, m_fixed=24, k_fixed=1)
     kw["ortho"] = ortho
