@@ -142,7 +142,7 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
     tuned_G = workgroups
     if workgroups == 0:
         # the project's autotuner picks the team size of the persistent kernel
-        tuned_G, tuned_ms = cal.autotune(prob.dt, m_trial=max(8, min(m_cal, 48)), trials=2)
+        tuned_G, tuned_ms = cal.autotune(prob.dt, m_trial=max(8, min(m_cal, 48)), trials=5)
         log(args, f"  {prob.name} {precision}: autotuned workgroups = {tuned_G} ({tuned_ms:.3f} ms/projection)")
     if adaptive:
         ctx = cal

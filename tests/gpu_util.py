@@ -45,5 +45,12 @@ def svk_of(prob):
     return prob.with_(name=prob.name + "-svk", model="svk", params=(2.0e6, 0.4e6))
 
 
+def yeoh_rubber_of(prob):
+    """The same problem with the full Yeoh solid: the rubber constants printed in Sec. 6.2.3
+    (C10 = 100, C20 = -1, C30 = 0.01, D1 = 0.001) read in kPa, with D1 scaled so that the
+    bulk-to-shear ratio 2/D1 : 2 C10 stays 10 (C20, C30 != 0: all three Yeoh terms active)."""
+    return prob.with_(name=prob.name + "-yeoh3", model="yeoh", params=(1.0e5, -1.0e3, 10.0, 1.0e-6))
+
+
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))

@@ -4,7 +4,7 @@ import pytest
 
 from workloads import config, distort
 from oracle import krylov
-from tests.gpu_util import from_gpu_vec, pair, rel, say, svk_of, to_gpu_vec
+from tests.gpu_util import from_gpu_vec, pair, rel, say, svk_of, to_gpu_vec, yeoh_rubber_of
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -32,6 +32,7 @@ CASES_H = [
     ("yeoh", "c4", dict(nx=4, ny=3, nz=3), True),
     ("svk", "c3", dict(nx=8, ny=2, nz=2), False),
     ("svk", "c3", dict(nx=8, ny=2, nz=2), True),
+    ("yeoh3", "c4", dict(nx=4, ny=3, nz=3), True),
 ]
 
 
@@ -43,6 +44,8 @@ def test_apply_H_matches_oracle(model, name, over, distorted, prec):
     p = config(name, **over)
     if model == "svk":
         p = svk_of(p)
+    elif model == "yeoh3":
+        p = yeoh_rubber_of(p)
     if distorted == "renumbered":
         p = renumbered(p)
     elif distorted:
@@ -147,7 +150,8 @@ def test_linear_steps_c1(mode, ortho):
 
 @pytest.mark.parametrize("model,name,over", [("nh", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4)),
                                               ("yeoh", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3)),
-                                              ("svk", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4))])
+                                              ("svk", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4)),
+                                              ("yeoh3", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3))])
 @pytest.mark.parametrize("mode", ["fixed", "adaptive"])
 @pytest.mark.parametrize("ortho", [0, 1])
 def test_nonlinear_steps(model, name, over, mode, ortho):
@@ -157,6 +161,8 @@ def test_nonlinear_steps(model, name, over, mode, ortho):
     p = config(name, **over)
     if model == "svk":
         p = svk_of(p)
+    elif model == "yeoh3":
+        p = yeoh_rubber_of(p)
     n = 12
     kw = dict(m_max=48) if mode == "adaptive" else dict(m_max=48, m_fixed=24, k_fixed=1)
     kw["ortho"] = ortho
