@@ -129,9 +129,9 @@ __device__ __forceinline__ int check_point(Team& tm, const ExpvArgs& A, int j, d
   const size_t Lp = (size_t)A.M.Lp;
   if (tm.rank == 0) {
     __syncthreads();
-    // two instantiations, so that the LDS one addresses its scratch as LDS
-    const double* E = (X.ex != nullptr && expm_scratch(j) <= X.ex_cap) ? wg_expm(W.H, ldH, j, X.ex, red, X.ired)
-                                                                       : wg_expm_global(W.H, ldH, j, W.Escr, red, X.ired);
+    // out of line (see wg_expm_call); scratch in LDS when it fits, else in device memory
+    double* scr = (X.ex != nullptr && expm_scratch(j) <= X.ex_cap) ? X.ex : W.Escr;
+    const double* E = wg_expm_call(W.H, ldH, j, scr, red, X.ired);
     const int le = expm_ld(j);
     const double eps = hn * beta * fabs(E[(size_t)(j - 1) * le]);
     int dec = 0;
