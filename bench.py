@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--matvec-only", action="store_true",
+                    help="only the stand-alone FP64 operator applies on the 64^3 and 128^3 cubes (profiling)")
     ap.add_argument("--tangents-only", action="store_true",
                     help="only the BF16 tangent formation / apply on the 64^3 Yeoh block (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -322,8 +324,8 @@ def run_batch(probs, precision, steps, m_max, stream, torch, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is "
-                                   "described in DESIGN.md but not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding over several "
+                                   "GPUs is not built)"}))
         sys.exit(2)
     import torch
     from workloads import config, batch_instances
@@ -335,6 +337,9 @@ def main():
     prob = config(args.config, dt=args.dt)
     if args.copy_probe:
         copy_probe(torch)
+    if args.matvec_only:
+        print(json.dumps(run_matvecs(config, stream, torch, args)))
+        return
     if args.tangents_only:
         cube = config("c4")
         u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
@@ -408,15 +413,9 @@ def main():
                         "energy": abs((en[0] + en[1] - en[2]) - (er[0] + er[1] - er[2])) / (er[0] + er[1])}
                 extra[f"{name}_{prec}"] = e
                 del r
-        import dataclasses
+        extra.update(run_matvecs(config, stream, torch, args))
         cube = config("c4")
-        for nx in (64, 128):
-            q = cube if nx == 64 else config("c4", nx=nx, ny=nx, nz=nx)
-            q = dataclasses.replace(q, model="linear", params=(200e9, 0.3), rho=7800.0)
-            extra[f"matvec_cube{nx}_linear_f64"] = run_matvec(q, None, 50, stream, torch, args)
-            del q
         u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
-        extra["matvec_cube64_yeoh_f64"] = run_matvec(cube, u_aff, 20, stream, torch, args)
         extra["tangents_cube64_yeoh_bf16"] = run_tangents(cube, u_aff, 20, stream, torch, args)
         probs = batch_instances(256, seed=5, dt=2.5e-5)
         for prec in ("f64", "mixed_f32"):
@@ -426,6 +425,22 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(prob, m_used, k_used, args)
     print(json.dumps(result))
+
+
+def run_matvecs(config, stream, torch, args):
+    """The stand-alone FP64 applies: linear 64^3 and 128^3 cubes (lattice path) and the Yeoh
+    secant apply on the 64^3 block at an affine deformation."""
+    import dataclasses
+    out = {}
+    cube = config("c4")
+    for nx in (64, 128):
+        q = cube if nx == 64 else config("c4", nx=nx, ny=nx, nz=nx)
+        q = dataclasses.replace(q, model="linear", params=(200e9, 0.3), rho=7800.0)
+        out[f"matvec_cube{nx}_linear_f64"] = run_matvec(q, None, 50, stream, torch, args)
+        del q
+    u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
+    out["matvec_cube64_yeoh_f64"] = run_matvec(cube, u_aff, 20, stream, torch, args)
+    return out
 
 
 def cpu_baseline(prob, m, k, args):

@@ -1,6 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark uses
 (needs an MI355X).  Where a whole oracle step would take minutes (the 64^3 block), the
 operator and the energies are compared at full size instead."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -65,3 +67,19 @@ def test_c4_full_operator_and_energy(prec, tol):
     o.t = 0.05
     ko, so, wo = o.energies()
     assert abs(ke - ko) <= 1e-12 * ko and abs(se - so) <= 1e-11 * so and abs(we - wo) <= 1e-12 * abs(wo)
+
+
+def test_lattice_apply_many_tiles():
+    """Linear lattice whose 79 x 71 x 87 interior nodes make 3 x 9 x 22 = 594 tiles of the
+    stencil apply (each cut in x, y and z at the far end), more tiles than the machine holds
+    at once: H x on all DOFs against the oracle."""
+    say("[full] lattice 80x72x88 apply")
+    p = dataclasses.replace(config("c4", nx=80, ny=72, nz=88), model="linear", params=(200e9, 0.3), rho=7800.0)
+    ctx, orc = pair(p, m_max=4)
+    assert ctx.launch()[2] == 2                        # the lattice path
+    x = np.random.default_rng(22).normal(size=3 * p.n_nodes)
+    y = torch.zeros(3 * p.n_nodes, dtype=torch.float64, device=DEV)
+    ctx.apply_H(None, _t(x), y)
+    err = rel(y.cpu().numpy(), orc.fem.H_apply(None, x))
+    say(f"  rel err {err:.2e}")
+    assert err < 1e-12
