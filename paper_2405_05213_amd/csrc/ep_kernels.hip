@@ -210,8 +210,10 @@ __global__ void k_reset_ctrl(Ctrl* c, int full) {
 // ---------------------------------------------------------------------------------------
 // stage kernels: operator apply as two launches (element forces, per-DOF gather)
 // ---------------------------------------------------------------------------------------
+// Two waves per SIMD at least: without the bound the FP64 Yeoh instance takes 256 VGPRs and
+// one AGPR, which leaves one wave per SIMD and the gathers' latency exposed.
 template <typename T, int MODEL>
-__global__ __launch_bounds__(256) void k_elem_forces(Mesh M, OpArgs op, const double* __restrict__ src,
+__global__ __launch_bounds__(256, 2) void k_elem_forces(Mesh M, OpArgs op, const double* __restrict__ src,
                                                      double srcscale, int scale_mih, T* __restrict__ F,
                                                      int* __restrict__ err) {
   constexpr int lanes = elem_lanes<T, MODEL>();
