@@ -384,6 +384,7 @@ def main():
             "alg_bytes_per_launch": alg, "avg_launch_ms": launch_s * 1e3,
         },
     }
+    _, u_head, v_head = head["ctx"].get_state()
     del head["ctx"]
 
     if not args.no_extra:
@@ -391,6 +392,11 @@ def main():
         mixed = run_single(prob, "mixed_f32", args.steps, args.warmup, args.m_max, args.workgroups, args.adaptive,
                            stream, torch, args)
         extra["c2_mixed_f32"] = {k: v for k, v in mixed.items() if k not in ("ctx", "step_ms")}
+        # the same steps as the FP64 headline run: error of the final state against it
+        _, u_mix, v_mix = mixed["ctx"].get_state()
+        extra["c2_mixed_f32"]["state_rel_err_vs_f64"] = {
+            "u": float(np.linalg.norm(u_mix - u_head) / np.linalg.norm(u_head)),
+            "v": float(np.linalg.norm(v_mix - v_head) / np.linalg.norm(v_head))}
         del mixed
         for name, dt, steps in (("c3", 1e-4, 20), ("c4", 1e-3, 8)):
             p = config(name, dt=dt)

@@ -244,3 +244,35 @@ def test_slices_in_device_memory(ortho):
     _, ur, vr = ref.get_state()
     assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
     assert rel(u, ur) < 1e-9 and rel(v, vr) < 1e-9
+
+
+# (model, workload, overrides, steps, tolerance on u, tolerance on v).  Measured errors: the
+# soft solids 4e-10 - 5e-8; the steel cantilever u 9.5e-7, v 4.1e-5 after 40 steps - its
+# smooth bending response is a small difference of large element forces (E = 200 GPa), so the
+# FP32 rounding of those forces (about 1e-7 relative) appears amplified about 1e3 times in the
+# velocity.  Tolerances keep a margin of about 5 over the measured errors.
+MIXED_STEP_CASES = [("linear", "c1", dict(dt=1e-4), 40, 5e-6, 2e-4),
+                    ("nh", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4), 12, 1e-6, 1e-6),
+                    ("yeoh", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3), 12, 1e-6, 1e-6),
+                    ("svk", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4), 12, 1e-6, 1e-6),
+                    ("yeoh3", "c4", dict(nx=3, ny=3, nz=3, dt=2e-3), 12, 1e-6, 1e-6)]
+
+
+@pytest.mark.parametrize("model,name,over,n,tol_u,tol_v", MIXED_STEP_CASES)
+def test_steps_mixed_f32(model, name, over, n, tol_u, tol_v):
+    """Time steps with the FP32 operator (Krylov, exponential and state in FP64) against the
+    FP64 oracle, fixed subspace so that both take the same path.  The operator's FP32
+    rounding is the only difference from the FP64 path."""
+    say(f"[steps mixed_f32] {model} {name} {over} n={n}")
+    p = config(name, **over)
+    if model == "svk":
+        p = svk_of(p)
+    elif model == "yeoh3":
+        p = yeoh_rubber_of(p)
+    ctx, orc = pair(p, m_max=48, m_fixed=24, k_fixed=1, precision="mixed_f32")
+    ctx.step(p.dt, n)
+    t, u, v = ctx.get_state()
+    orc.run(p.dt, n)
+    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    say(f"  rel err u {eu:.2e} v {ev:.2e}")
+    assert eu < tol_u and ev < tol_v
