@@ -532,8 +532,8 @@ void launch_stencil_blocks(const double* Ke, double* B, hipStream_t st) { k_sten
 // contiguous doubles in device memory, loaded by whole waves, every load issued before the
 // first LDS store).  Each thread applies the 27 blocks B_o to kLU consecutive nodes along x:
 // for each (j, k) offset it reads the kLU + 2 halo columns once and uses them for all kLU
-// nodes (40.5 LDS reads per node instead of 81, 243 FMAs per node).  The B_o addresses are
-// uniform (scalar loads).  Lattice boundary nodes are left to k_apply_lattice_bnd.
+// nodes (54 LDS reads per node instead of 81, 243 FMAs per node).  The B_o addresses are
+// uniform (scalar loads).  Lattice boundary nodes are left to lattice_boundary_block.
 constexpr int kLU = 2, kLX = 32, kLY = 8, kLZ = 4;
 constexpr int kLTX = kLX / kLU;
 constexpr int kLThreads = kLTX * kLY * kLZ;
