@@ -256,7 +256,10 @@ ep_status ep_expv(ep_ctx* ctx, const double* u_lin_dev, double tau, double pscal
  * state) together: every instance's projections run inside one persistent launch per
  * step, one workgroup per instance, each with its own subspace size.  Instances are
  * added after ep_create and before ep_bind_workspace; the single-instance setup calls
- * are then not used.  The Krylov / precision settings apply to all instances. */
+ * are then not used.  The Krylov / precision settings apply to all instances.
+ * Device-side failures are per instance: a failed instance stops advancing while the
+ * others go on; its ep_batch_get_state / ep_batch_get_energy return the error (sticky),
+ * ep_sync returns the first failed instance's, and ep_batch_set_state clears it. */
 ep_status ep_batch_add_instance(ep_ctx* ctx, int64_t n_nodes, const double* xyz_host,
                                 int64_t n_elems, const int32_t* conn_host, ep_model model,
                                 const double* params_host, int n_params, double rho,

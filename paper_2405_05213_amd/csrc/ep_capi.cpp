@@ -1298,7 +1298,8 @@ ep_status ep_batch_get_state(ep_ctx* c, int32_t id, double* t, double* u, double
   ep_status s = need_batch(c, id);
   if (s != EP_OK) return s;
   if (!t || !u || !v) return fail(c, EP_ERR_ARG, "null output");
-  s = ep_sync(c);
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  s = read_err(c, c->insts[id]);                 // this instance's failure only
   if (s != EP_OK) return s;
   s = pull_record(c, id);
   if (s != EP_OK) return s;
@@ -1330,7 +1331,8 @@ ep_status ep_batch_get_energy(ep_ctx* c, int32_t id, double* ke, double* se, dou
   ep_status s = need_batch(c, id);
   if (s != EP_OK) return s;
   if (!ke || !se || !we) return fail(c, EP_ERR_ARG, "null output");
-  s = ep_sync(c);
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  s = read_err(c, c->insts[id]);                 // this instance's failure only
   if (s != EP_OK) return s;
   s = pull_record(c, id);
   if (s != EP_OK) return s;
