@@ -260,6 +260,9 @@ ep_status ep_expv(ep_ctx* ctx, const double* u_lin_dev, double tau, double pscal
  * Device-side failures are per instance: a failed instance stops advancing while the
  * others go on; its ep_batch_get_state / ep_batch_get_energy return the error (sticky),
  * ep_sync returns the first failed instance's, and ep_batch_set_state clears it. */
+/* Add one instance (Sec. 2.2 setup): the arguments are those of ep_set_mesh_hex8,
+ * ep_set_material, ep_set_dirichlet and ep_set_traction in that order (host arrays, copied
+ * at the call).  *instance_id receives its index; ids are consecutive from 0. */
 ep_status ep_batch_add_instance(ep_ctx* ctx, int64_t n_nodes, const double* xyz_host,
                                 int64_t n_elems, const int32_t* conn_host, ep_model model,
                                 const double* params_host, int n_params, double rho,
@@ -268,9 +271,16 @@ ep_status ep_batch_add_instance(ep_ctx* ctx, int64_t n_nodes, const double* xyz_
                                 const double t0_host[3], int64_t n_knots,
                                 const double* t_knots_host, const double* scale_host,
                                 int32_t* instance_id);
+/* As ep_set_state, for one instance: also clears its predictor history and its failure. */
 ep_status ep_batch_set_state(ep_ctx* ctx, int32_t instance_id, double t, const double* u_host,
                              const double* v_host);
+/* Advance every instance n_steps steps of size dt (linear instances: one propagation per
+ * step; nonlinear: predictor and corrector, Sec. 4.2).  One step is one persistent launch
+ * per material model present, captured into a graph on the first call with this dt and
+ * replayed n_steps times on the context's stream (asynchronous); every instance needs a
+ * state first (EP_ERR_ORDER). */
 ep_status ep_batch_step(ep_ctx* ctx, double dt, int64_t n_steps);
+/* As ep_get_state, for one instance (synchronising; returns that instance's failure only). */
 ep_status ep_batch_get_state(ep_ctx* ctx, int32_t instance_id, double* t, double* u_host,
                              double* v_host);
 /* Per-instance statistics of the last step: corrector m and substeps. */
