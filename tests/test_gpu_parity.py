@@ -209,12 +209,13 @@ def test_congruence_detection(name, over, mode, expect):
     assert g >= 1 and chunk >= 64 and g * chunk >= 2 * 3 * p.n_nodes + 1
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-7), ("mixed_f32", 1e-5)])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-7), ("mixed_f32", 3e-5)])
 def test_energy_conservation_free_vibration(prec, tol):
     """Unloaded cantilever with random initial velocity, 60 adaptive steps: the propagator
     conserves the discrete energy up to the Krylov tolerance (FP64: ~1e-8 measured) and the
-    FP32 operator's rounding (measured ~5e-6; an element kernel that loses the deformation to
-    a large common translation drifts by ~1e-3)."""
+    FP32 operator's rounding: 5e-6 - 1.6e-5 measured, depending on the adaptive path (small
+    exponential implementations that agree to 1e-13 change the subspace size at some steps);
+    an element kernel that loses the deformation to a large common translation drifts 1e-3."""
     say(f"[energy] c2 20x4x4 {prec}")
     p = config("c2", nx=20, ny=4, nz=4)
     ctx, _ = pair(p, precision=prec, m_max=64)
