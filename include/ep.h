@@ -9,7 +9,7 @@
  *   midpoint rule, Sec. 3.3 and 4.1) with a predictor-corrector for the nonlinear
  *   H at the midpoint (Sec. 4.2).  exp(dt A) wbar is evaluated by Arnoldi (modified
  *   Gram-Schmidt) with the subspace error estimate choosing the subspace size and
- *   exp(H_m) by Taylor / scaling-and-squaring Pade (Sec. 4.3).
+ *   exp(H_m) by Taylor with scaling and squaring (Sec. 4.3).
  *
  * Discretisation: 8-node hexahedra (VTK node order), 2x2x2 Gauss quadrature for the
  *   internal force, vertex (2-point Gauss-Lobatto) rule for a diagonal mass, 2x2 Gauss
@@ -235,7 +235,7 @@ ep_status ep_apply_A(ep_ctx* ctx, const double* u_lin_dev, double tau, double ps
 ep_status ep_vector_length(ep_ctx* ctx, int64_t* length, int64_t* padded_length);
 
 /* E = exp(H) for a dense m x m row-major matrix (m <= 256) on one workgroup:
- * Taylor if ||H||_1 <= 1, else scaling and squaring with the [13/13] Pade approximant
+ * degree-18 Taylor polynomial, applied to H / 2^s and squared s times when ||H||_1 > 1
  * (Sec. 4.3).  Host arrays. */
 ep_status ep_expm(ep_ctx* ctx, int m, const double* H_host, double* E_host);
 

@@ -100,7 +100,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double
   return true;
 }
 
-// doubles of LDS before the slice buffers: red[32] | yb[kMaxM] | ints flag[16], ired[16]
+// doubles of LDS before the slice buffers: red[32] | yb[kMaxM] | ints flag[16], 16 unused
 constexpr int kBatchHead = 32 + kMaxM + 16;
 
 template <typename T, int MODEL>
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
   int* flag = (int*)(lds + 32 + kMaxM);
   // the slice region (lds_slices doubles) doubles as expm scratch: the sequential form
   // reloads both slice buffers after a check point
-  const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, flag + 16, true};
+  const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, true};
   if (threadIdx.x == 0) *flag = 1;
   __syncthreads();
   const int id = ids[blockIdx.x];

@@ -1,8 +1,10 @@
 // exp(H) of a small dense matrix on one workgroup (Sec. 4.3 of the paper: Taylor series
-// when ||H|| <= 1, scaling and squaring otherwise, no eigendecomposition).  The squaring
-// branch uses the degree-13 diagonal Pade approximant and the scaling rule of Higham,
-// "The scaling and squaring method for the matrix exponential revisited", SIAM J. Matrix
-// Anal. Appl. 26 (2005): s = max(0, ceil(log2(||H||_1 / theta_13))).
+// when ||H|| <= 1, scaling and squaring otherwise, no eigendecomposition).  The Taylor
+// polynomial has the fixed degree 18 and is evaluated in the Paterson-Stockmeyer form
+// (Paterson & Stockmeyer, SIAM J. Comput. 2 (1973)): 7 matrix products; when ||H||_1 > 1 it
+// is applied to H / 2^s, s = ceil(log2 ||H||_1), and squared s times.  Only matrix products
+// (on the FP64 matrix cores) and elementwise passes: no linear solve, whose column-by-column
+// latency on one workgroup would exceed all the products together.
 // Matrices are row major with leading dimension m and live in LDS when they fit, else in
 // device memory private to the calling workgroup; every thread of the workgroup must call.
 #pragma once
@@ -11,30 +13,32 @@
 
 namespace ep {
 
-constexpr double kTheta13 = 5.371920351148152;
+// Degree and scaling threshold: for ||A||_1 <= 1 the omitted terms sum to at most
+// sum_{k > 18} 1/k! = 8.7e-18 in norm, and ||e^A|| >= e^{-||A||} >= e^{-1}, so the relative
+// truncation error stays below 2.4e-17, under the unit roundoff 2^-53.
+constexpr int kTaylorDeg = 18;
+constexpr double kTaylorTheta = 1.0;
 
-// numerator coefficient c_j of the [13/13] Pade approximant: (26-j)! 13! / (26! j! (13-j)!),
-// built by the ratio c_j / c_{j-1} = (13 - j + 1) / (j (26 - j + 1)); evaluated at compile time
-struct Pade13 {
-  double c[14];
-  constexpr Pade13() : c{} {
+// 1/k!, k = 0..18, evaluated at compile time
+struct Taylor18 {
+  double c[kTaylorDeg + 1];
+  constexpr Taylor18() : c{} {
     double v = 1.0;
-    c[0] = 1.0;
-    for (int j = 1; j <= 13; ++j) {
-      v *= double(13 - j + 1) / double(j * (26 - j + 1));
-      c[j] = v;
+    for (int k = 0; k <= kTaylorDeg; ++k) {
+      if (k > 0) v /= double(k);
+      c[k] = v;
     }
   }
 };
-__device__ constexpr Pade13 kPade13{};
+__device__ constexpr Taylor18 kTaylor18{};
 
 __device__ __forceinline__ void wg_sync() { __syncthreads(); }
 
 // Leading dimension of the work matrices: odd for even m >= 8, so that the 16 rows of a
 // matrix-core fragment fall in distinct LDS banks.
 __host__ __device__ __forceinline__ int expm_ld(int m) { return (m >= 8 && (m & 1) == 0) ? m + 1 : m; }
-// doubles of scratch wg_expm needs: six m x ld matrices and two m-vectors
-__host__ __device__ __forceinline__ int expm_scratch(int m) { return 6 * m * expm_ld(m) + 2 * m; }
+// doubles of scratch wg_expm needs: six m x ld matrices
+__host__ __device__ __forceinline__ int expm_scratch(int m) { return 6 * m * expm_ld(m); }
 
 // C = A * B on the FP64 matrix cores: each wave computes 16 x 16 tiles of C with
 // v_mfma_f64_16x16x4 (A fragment 16 x 4: lane l holds A[l % 16][l / 16]; B fragment
@@ -89,159 +93,60 @@ __device__ __forceinline__ double wg_norm1(const double* A, int m, int ld, doubl
   return r;
 }
 
-// Solve A X = B (A destroyed, B <- X) by Gaussian elimination with partial pivoting
-// (ties: smallest row index).  Per column k: wave 0 finds the pivot row; rows k and p are
-// exchanged in the columns still needed (A columns > k, all of B) while the multipliers
-// l_r = A[r][k] / A[p][k] (after the exchange) go to mult[] and the pivot to diag[k]; then
-// the trailing update, a thread per column and every ng-th row.  The back substitution
-// gives every column of B eight lanes of one wave.  diag, mult: m doubles; ired: >= 1 int.
-__device__ __forceinline__ void wg_solve(double* A, double* B, int m, int ld, double* diag, double* mult, int* ired) {
-  for (int k = 0; k < m; ++k) {
-    if (threadIdx.x < 64) {
-      double best = -1.0;
-      int bi = m;
-      for (int r = k + (int)threadIdx.x; r < m; r += 64) {
-        const double v = fabs(A[(size_t)r * ld + k]);
-        if (v > best) { best = v; bi = r; }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (threadIdx.x == 0) ired[0] = bi < m ? bi : k;
-    }
-    __syncthreads();
-    const int p = ired[0];
-    const double piv = A[(size_t)p * ld + k];
-    const int ca = m - k - 1;                 // A columns k+1..m-1, then the m columns of B
-    const int cols = ca + m;
-    for (int c = threadIdx.x; c < cols; c += blockDim.x) {
-      if (p == k) break;
-      double* X = c < ca ? A : B;
-      const int j = c < ca ? k + 1 + c : c - ca;
-      const double t = X[(size_t)k * ld + j];
-      X[(size_t)k * ld + j] = X[(size_t)p * ld + j];
-      X[(size_t)p * ld + j] = t;
-    }
-    for (int r = k + 1 + (int)threadIdx.x; r < m; r += blockDim.x)
-      mult[r] = (r == p ? A[(size_t)k * ld + k] : A[(size_t)r * ld + k]) / piv;
-    if (threadIdx.x == 0) diag[k] = piv;
-    __syncthreads();
-    const int ng = cols <= (int)blockDim.x ? (int)blockDim.x / cols : 1;
-    for (int idx = threadIdx.x; idx < ng * cols; idx += blockDim.x) {
-      const int c = idx % cols, g = idx / cols;
-      double* X = c < ca ? A : B;
-      const int j = c < ca ? k + 1 + c : c - ca;
-      const double xk = X[(size_t)k * ld + j];
-      for (int r = k + 1 + g; r < m; r += ng) X[(size_t)r * ld + j] -= mult[r] * xk;
-    }
-    __syncthreads();
-  }
-  // back substitution: lanes 8g..8g+7 take column j, splitting each row sum by c mod 8
-  const int r8 = threadIdx.x & 7;
-  for (int j = threadIdx.x >> 3; j < m; j += blockDim.x >> 3) {
-    for (int k = m - 1; k >= 0; --k) {
-      double s = 0.0;
-      for (int c = k + 1 + r8; c < m; c += 8) s += A[(size_t)k * ld + c] * B[(size_t)c * ld + j];
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 4, 64);
-      const double x = (B[(size_t)k * ld + j] - s) / diag[k];
-      if (r8 == (k & 7)) B[(size_t)k * ld + j] = x;   // later read only by this lane
-    }
-  }
-  __syncthreads();
-}
-
 // E = exp(Hin).  Hin is m x m with leading dimension ldh; E is returned inside scr with
 // leading dimension expm_ld(m).  scr: expm_scratch(m) doubles private to the workgroup
-// (LDS or device memory).
-__device__ __forceinline__ double* wg_expm(const double* Hin, int ldh, int m, double* scr, double* red, int* ired) {
+// (LDS or device memory); red: one double per wave.
+__device__ __forceinline__ double* wg_expm(const double* Hin, int ldh, int m, double* scr, double* red) {
   const int ld = expm_ld(m);
   const size_t mm = (size_t)m * ld;
-  double* B0 = scr;
-  double* B1 = scr + mm;
-  double* B2 = scr + 2 * mm;
-  double* B3 = scr + 3 * mm;
-  double* B4 = scr + 4 * mm;
-  double* B5 = scr + 5 * mm;
-  double* diag = scr + 6 * mm;
-  double* mult = diag + m;
+  double* A = scr;
+  double* A2 = scr + mm;
+  double* A3 = scr + 2 * mm;
+  double* A4 = scr + 3 * mm;
+  double* X = scr + 4 * mm;
+  double* Y = scr + 5 * mm;
   const int n = m * ld;
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int i = idx / ld, j = idx - i * ld;
-    if (j < m) B0[idx] = Hin[(size_t)i * ldh + j];
+    if (j < m) A[idx] = Hin[(size_t)i * ldh + j];
   }
   wg_sync();
-  const double nrm = wg_norm1(B0, m, ld, red);
-  if (nrm <= 1.0) {
-    // Taylor: E = sum_k A^k / k!, stopped when the term's norm drops below 2^-53 ||E||
-    double* E = B1;
-    double* Tm = B2;
-    double* T1 = B3;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-      const int i = idx / ld, j = idx - i * ld;
-      E[idx] = (i == j) ? 1.0 : 0.0;
-      Tm[idx] = (i == j) ? 1.0 : 0.0;
-    }
-    wg_sync();
-    for (int k = 1; k <= 60; ++k) {
-      wg_gemm(Tm, B0, T1, m, ld);
-      const double inv = 1.0 / double(k);
-      for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        const double t = T1[idx] * inv;
-        Tm[idx] = t;
-        E[idx] += t;
-      }
-      wg_sync();
-      const double tn = wg_norm1(Tm, m, ld, red);
-      const double en = wg_norm1(E, m, ld, red);
-      if (tn <= 0x1p-53 * en) break;
-    }
-    return E;
-  }
-  // s = max(0, ceil(log2(||A||_1 / theta_13))): halvings are exact, so this is the least s
-  // with ||A||_1 / theta_13 / 2^s <= 1
+  // s = max(0, ceil(log2(||H||_1 / theta))): halvings are exact, so this is the least s with
+  // ||H||_1 / theta / 2^s <= 1
+  const double nrm = wg_norm1(A, m, ld, red);
   int s = 0;
   double sc = 1.0;
-  for (double r = nrm / kTheta13; r > 1.0 && s < 1024; r *= 0.5) {
+  for (double r = nrm / kTaylorTheta; r > 1.0 && s < 1024; r *= 0.5) {
     ++s;
     sc *= 0.5;
   }
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) B0[idx] *= sc;   // A
-  wg_sync();
-  const double* c = kPade13.c;
-  wg_gemm(B0, B0, B1, m, ld);      // A2
-  wg_gemm(B1, B1, B2, m, ld);      // A4
-  wg_gemm(B2, B1, B3, m, ld);      // A6
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x)
-    B4[idx] = c[13] * B3[idx] + c[11] * B2[idx] + c[9] * B1[idx];
-  wg_sync();
-  wg_gemm(B3, B4, B5, m, ld);      // A6 (c13 A6 + c11 A4 + c9 A2)
+  if (s > 0) {
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) A[idx] *= sc;
+    wg_sync();
+  }
+  const double* c = kTaylor18.c;
+  wg_gemm(A, A, A2, m, ld);
+  wg_gemm(A2, A, A3, m, ld);
+  wg_gemm(A2, A2, A4, m, ld);
+  // T(A) = B_0 + A^4 (B_1 + A^4 (B_2 + A^4 (B_3 + A^4 B_4))), B_j = sum_{i<4} c_{4j+i} A^i
+  // (B_4 = c_16 I + c_17 A + c_18 A^2): Horner's rule in A^4
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int i = idx / ld, j = idx - i * ld;
-    B5[idx] += c[7] * B3[idx] + c[5] * B2[idx] + c[3] * B1[idx] + ((i == j) ? c[1] : 0.0);
+    X[idx] = c[17] * A[idx] + c[18] * A2[idx] + ((i == j) ? c[16] : 0.0);
   }
   wg_sync();
-  wg_gemm(B0, B5, B4, m, ld);      // U = A (A6 (...) + c7 A6 + c5 A4 + c3 A2 + c1 I)
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x)
-    B5[idx] = c[12] * B3[idx] + c[10] * B2[idx] + c[8] * B1[idx];
-  wg_sync();
-  wg_gemm(B3, B5, B0, m, ld);      // A6 (c12 A6 + c10 A4 + c8 A2); A is no longer needed
-  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-    const int i = idx / ld, j = idx - i * ld;
-    const double v = B0[idx] + c[6] * B3[idx] + c[4] * B2[idx] + c[2] * B1[idx] + ((i == j) ? c[0] : 0.0);
-    const double u = B4[idx];
-    B0[idx] = v - u;               // Q = V - U
-    B4[idx] = v + u;               // P = V + U
+  for (int b = 3; b >= 0; --b) {
+    wg_gemm(A4, X, Y, m, ld);
+    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+      const int i = idx / ld, j = idx - i * ld;
+      X[idx] = Y[idx] + c[4 * b + 1] * A[idx] + c[4 * b + 2] * A2[idx] + c[4 * b + 3] * A3[idx] +
+               ((i == j) ? c[4 * b] : 0.0);
+    }
+    wg_sync();
   }
-  wg_sync();
-  wg_solve(B0, B4, m, ld, diag, mult, ired);    // R = Q^{-1} P
-  double* R = B4;
-  double* Rn = B1;
-  for (int qq = 0; qq < s; ++qq) {
+  double* R = X;
+  double* Rn = Y;
+  for (int q = 0; q < s; ++q) {
     wg_gemm(R, R, Rn, m, ld);
     double* t = R; R = Rn; Rn = t;
   }
@@ -252,9 +157,8 @@ __device__ __forceinline__ double* wg_expm(const double* Hin, int ldh, int m, do
 // the Krylov kernels call it at check points only, and keeping its matrix-core and solve
 // code out of their Arnoldi loop lowers that loop's register spills (c2: 7.15 -> 6.83 ms per
 // step) by more than the generic LDS addressing costs the exponential.
-__device__ __noinline__ double* wg_expm_call(const double* Hin, int ldh, int m, double* scr, double* red,
-                                             int* ired) {
-  return wg_expm(Hin, ldh, m, scr, red, ired);
+__device__ __noinline__ double* wg_expm_call(const double* Hin, int ldh, int m, double* scr, double* red) {
+  return wg_expm(Hin, ldh, m, scr, red);
 }
 
 }  // namespace ep

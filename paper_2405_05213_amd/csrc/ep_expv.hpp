@@ -9,7 +9,7 @@
 namespace ep {
 
 // LDS: red[32] | yb[kMaxM] | ke[24 kKeLd] | (compact WY: T[m_max^2] | vals[2 m_max] | gp[kThreads]) |
-//      ints: flag[16], ired[16] | region U: the slice buffers lw, lv (2 chunk, SG = 0 only)
+//      ints: flag[16], 16 unused | region U: the slice buffers lw, lv (2 chunk, SG = 0 only)
 //      overlaid with the check point's expm scratch (ex_cap doubles)
 __host__ __device__ inline size_t expv_head_doubles(int ortho, int m_max) {
   size_t d = 32 + kMaxM + 24 * kKeLd + 16;
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   double* yb = red + 32;
   double* ke = yb + kMaxM;
   double* p = ke + 24 * kKeLd;
-  KLds X{nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr, SG == 0};
+  KLds X{nullptr, nullptr, nullptr, nullptr, nullptr, 0, SG == 0};
   if (MODEL == kLinear && sizeof(T) == 8 && A.M.ke != nullptr) {
     for (int i = threadIdx.x; i < 24 * kKeLd; i += blockDim.x) ke[i] = A.M.ke[i];
     X.ke = ke;
@@ -41,7 +41,6 @@ __global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   }
   int* ints = (int*)p;
   int* flag = ints;
-  X.ired = ints + 16;
   double* U = p + 16;
   double* lw;
   double* lv;

@@ -269,8 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_expm(int m, const double* __restri
                                                    double* __restrict__ scr, int use_lds) {
   extern __shared__ double dyn[];
   __shared__ double red[16];
-  __shared__ int ired[16];
-  const double* R = use_lds ? wg_expm(H, m, m, dyn, red, ired) : wg_expm_call(H, m, m, scr, red, ired);
+  const double* R = use_lds ? wg_expm(H, m, m, dyn, red) : wg_expm_call(H, m, m, scr, red);
   const int ld = expm_ld(m);
   for (int i = threadIdx.x; i < m * m; i += blockDim.x) E[i] = R[(size_t)(i / m) * ld + (i % m)];
 }

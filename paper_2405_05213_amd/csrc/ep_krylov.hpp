@@ -41,7 +41,7 @@ struct BlockTeam {
 // LDS scratch of a projection: T (m_max x m_max, row major), the step's inner products
 // (2 m_max) and reduction partials (blockDim.x) of the compact-WY form; the region ex of
 // ex_cap doubles that the check point may use for exp(H_j) (it overlays the slice buffers,
-// which the check does not need); integer scratch of the pivoting solve.
+// which the check does not need).
 struct KLds {
   double* ke;                 // rest-state element stiffness (T-typed, 24 x kKeLd) or null
   double* T;
@@ -49,7 +49,6 @@ struct KLds {
   double* gp;
   double* ex;
   int ex_cap;
-  int* ired;
   bool ex_aliases;            // ex overlays the slice buffers (reload v_j after a check)
 };
 
@@ -131,7 +130,7 @@ __device__ __forceinline__ int check_point(Team& tm, const ExpvArgs& A, int j, d
     __syncthreads();
     // out of line (see wg_expm_call); scratch in LDS when it fits, else in device memory
     double* scr = (X.ex != nullptr && expm_scratch(j) <= X.ex_cap) ? X.ex : W.Escr;
-    const double* E = wg_expm_call(W.H, ldH, j, scr, red, X.ired);
+    const double* E = wg_expm_call(W.H, ldH, j, scr, red);
     const int le = expm_ld(j);
     const double eps = hn * beta * fabs(E[(size_t)(j - 1) * le]);
     int dec = 0;
