@@ -154,9 +154,9 @@ __device__ __forceinline__ double* wg_expm(const double* Hin, int ldh, int m, do
 }
 
 // Out-of-line variant (scratch in LDS or device memory, reached through generic addresses):
-// the Krylov kernels call it at check points only, and keeping its matrix-core and solve
-// code out of their Arnoldi loop lowers that loop's register spills (c2: 7.15 -> 6.83 ms per
-// step) by more than the generic LDS addressing costs the exponential.
+// the Krylov kernels call it at check points only, and keeping its matrix-core code out of
+// their Arnoldi loop lowers that loop's register spills (c2 with the earlier Pade form of the
+// exponential: 7.15 -> 6.83 ms per step) by more than the generic LDS addressing costs it.
 __device__ __noinline__ double* wg_expm_call(const double* Hin, int ldh, int m, double* scr, double* red) {
   return wg_expm(Hin, ldh, m, scr, red);
 }
