@@ -76,6 +76,30 @@ def test_expm_matches_oracle(m, scale):
     assert np.abs(E - R).max() <= 1e-13 * max(1.0, np.abs(R).max()) * max(1.0, scale / 10)
 
 
+def test_expm_closed_forms():
+    """exp(H) on the GPU against closed forms, independent of the oracle: 1 x 1 matrices (the
+    scalar exponential, up to 6 squarings), 2 x 2 rotation generators (cos / sin, up to 7
+    squarings), the zero matrix (the identity, exactly) and a nilpotent matrix (its finite
+    Taylor sum)."""
+    import math
+    say("[expm] closed forms")
+    ctx, _ = pair(config("c1"), m_max=256)
+    for h in (-30.0, -1.0, 0.0, 0.5, 3.0, 40.0):
+        e = ctx.expm(np.array([[h]]))[0, 0]
+        assert abs(e - math.exp(h)) <= 1e-14 * math.exp(h) * max(1.0, abs(h)), h
+    for th in (0.3, 5.0, 100.0):
+        E = ctx.expm(np.array([[0.0, -th], [th, 0.0]]))
+        R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+        assert np.abs(E - R).max() <= 1e-15 * max(1.0, th), th
+    assert np.array_equal(ctx.expm(np.zeros((5, 5))), np.eye(5))
+    N = np.triu(np.random.default_rng(7).normal(size=(6, 6)), 1)
+    S, P = np.eye(6), np.eye(6)
+    for k in range(1, 6):
+        P = P @ N / k
+        S = S + P
+    assert np.abs(ctx.expm(N) - S).max() <= 1e-14 * np.abs(S).max()
+
+
 @pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("name,over,workgroups", [("c1", {}, 1), ("c1", {}, 4), ("c2", dict(nx=20, ny=4, nz=4), 0),
                                                   ("c2", dict(nx=20, ny=4, nz=4), 37)])
