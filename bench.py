@@ -398,6 +398,18 @@ def main():
             "u": float(np.linalg.norm(u_mix - u_head) / np.linalg.norm(u_head)),
             "v": float(np.linalg.norm(v_mix - v_head) / np.linalg.norm(v_head))}
         del mixed
+        # the c2 workload's time-step sweep (FP64): the subspace size and substeps the adaptive
+        # choice settles on, and the cost of one simulated second at each step size
+        sweep = {}
+        for dt in (1e-5, 1e-4, 1e-3):
+            r = run_single(config(args.config, dt=dt), "f64", 10, 3, args.m_max, args.workgroups, False,
+                           stream, torch, args)
+            sweep[f"{dt:g}"] = {"ms_per_step": r["ms_per_step"], "m": r["m"], "k": r["k"],
+                                "time_steps_per_s": r["time_steps_per_s"],
+                                "dof_matvecs_per_s": r["dof_matvecs_per_s"],
+                                "gpu_s_per_simulated_s": r["ms_per_step"] / 1e3 / dt}
+            del r
+        extra["c2_dt_sweep_f64"] = sweep
         for name, dt, steps in (("c3", 1e-4, 20), ("c4", 1e-3, 8)):
             p = config(name, dt=dt)
             ref_state = None
