@@ -19,27 +19,37 @@ def _t(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
 
 
-def test_c2_full_step():
-    """80x8x8 linear cantilever, dt = 1e-4, the benchmark's calibrated mode (m = 48, 4 substeps)."""
-    say("[full] c2 one step m=48 k=4")
+@pytest.mark.parametrize("prec,tol_u,tol_v", [("f64", 1e-8, 1e-8), ("mixed_f32", 5e-6, 5e-5)])
+def test_c2_full_step(prec, tol_u, tol_v):
+    """80x8x8 linear cantilever, dt = 1e-4, the benchmark's calibrated mode (m = 48, 4 substeps).
+    FP32 operator: measured u 8e-7, v 9.5e-6 (the steel beam's small net forces amplify the
+    FP32 rounding of the element forces, most in the velocity); tolerances about 5x that."""
+    say(f"[full] c2 one step m=48 k=4 {prec}")
     p = config("c2")
-    ctx, orc = pair(p, m_max=64, m_fixed=48, k_fixed=4)
+    ctx, orc = pair(p, m_max=64, m_fixed=48, k_fixed=4, precision=prec)
     ctx.step(p.dt, 1)
     t, u, v = ctx.get_state()
     orc.step(p.dt)
-    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
+    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    say(f"  rel err u {eu:.2e} v {ev:.2e}")
+    assert eu < tol_u and ev < tol_v
 
 
-def test_c3_full_step():
-    """160x16x16 compressible Neo-Hookean cantilever, first predictor-corrector step."""
-    say("[full] c3 one step")
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-8), ("mixed_f32", 5e-8), ("mixed_bf16", 5e-4)])
+def test_c3_full_step(prec, tol):
+    """160x16x16 compressible Neo-Hookean cantilever, first predictor-corrector step.  Measured:
+    FP32 operator 4e-9 / 8e-9, BF16 tangents 4e-5 / 8e-5 (u / v); tolerances about 5x that."""
+    say(f"[full] c3 one step {prec}")
     p = config("c3")
-    ctx, orc = pair(p, m_max=64)
+    ctx, orc = pair(p, m_max=64, precision=prec)
     ctx.step(p.dt, 1)
     t, u, v = ctx.get_state()
     orc.step(p.dt)
-    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
-    assert ctx.step_log(1)["m_corr"][0] == orc.log[0]["corr"]["m"][0]
+    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    say(f"  rel err u {eu:.2e} v {ev:.2e}")
+    assert eu < tol and ev < tol
+    if prec == "f64":
+        assert ctx.step_log(1)["m_corr"][0] == orc.log[0]["corr"]["m"][0]
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("mixed_f32", 3e-6), ("mixed_bf16", 1e-2)])
