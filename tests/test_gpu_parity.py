@@ -301,3 +301,25 @@ def test_steps_mixed_f32(model, name, over, n, tol_u, tol_v):
     eu, ev = rel(u, orc.u()), rel(v, orc.v())
     say(f"  rel err u {eu:.2e} v {ev:.2e}")
     assert eu < tol_u and ev < tol_v
+
+
+@pytest.mark.parametrize("name,over", [("c2", dict(nx=20, ny=4, nz=4)), ("c3", dict(nx=8, ny=2, nz=2))])
+def test_autotune_keeps_state_and_parity(name, over):
+    """The launch autotuner times projections of the current operator without touching the
+    state, leaves the context on the fastest team size it found, and steps from there agree
+    with the oracle."""
+    say(f"[autotune] {name} {over}")
+    p = config(name, **over)
+    ctx, orc = pair(p, m_max=48)
+    ctx.step(p.dt, 2)
+    t0, u0, v0 = ctx.get_state()
+    G, ms = ctx.autotune(p.dt, m_trial=16, trials=2)
+    say(f"  G = {G}, {ms:.3f} ms per projection")
+    assert G >= 1 and ms > 0.0
+    assert ctx.launch()[0] == G
+    t1, u1, v1 = ctx.get_state()
+    assert t1 == t0 and np.array_equal(u1, u0) and np.array_equal(v1, v0)
+    ctx.step(p.dt, 3)
+    t, u, v = ctx.get_state()
+    orc.run(p.dt, 5)
+    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
