@@ -107,6 +107,24 @@ __device__ __forceinline__ T log_ratio(T x) {
   return ep_log1p(x) / x;
 }
 
+// J^{-2/3} for J = 1 + x > 0.  FP64: an FP32 estimate of y = J^{-1/3} refined by two Newton
+// steps on y^{-3} = J, y <- y (4 - J y^3) / 3, whose error squares at each step (2e-6 ->
+// 1e-11 -> rounding; 8e-16 relative over 0.05 <= J <= 20), instead of two FP64 library
+// transcendentals; outside 1e-30 < J < 1e30, beyond the FP32 estimate's range, and in FP32,
+// the logarithmic form exp(-2/3 ln(1 + x)).
+template <typename T>
+__device__ __forceinline__ T j_pow_m23(T J, T x) {
+  if constexpr (sizeof(T) == 8) {
+    if (J > 1e-30 && J < 1e30) {
+      double y = (double)exp2f(-log2f((float)J) * (1.0f / 3.0f));
+      y = y * (4.0 - J * y * y * y) * (1.0 / 3.0);
+      y = y * (4.0 - J * y * y * y) * (1.0 / 3.0);
+      return y * y;
+    }
+  }
+  return ep_exp(T(-2.0 / 3.0) * ep_log1p(x));
+}
+
 // Returns false if J <= 0 (or not finite).
 template <typename T, int MODEL>
 __device__ __forceinline__ bool secant_coeffs(const T (&D)[3][3], const double* mp, Secant<T>& s) {
@@ -153,7 +171,7 @@ __device__ __forceinline__ bool secant_coeffs(const T (&D)[3][3], const double* 
       for (int k = 0; k < 3; ++k) s.W[i][k] = f * Qm[i][k];
   } else {   // Yeoh
     const T C10 = T(mp[0]), C20 = T(mp[1]), C30 = T(mp[2]), D1 = T(mp[3]);
-    const T Jm23 = ep_exp(T(-2.0 / 3.0) * ep_log1p(x));
+    const T Jm23 = j_pow_m23(J, x);
     T I1 = T(0);
 #pragma unroll
     for (int i = 0; i < 3; ++i)
