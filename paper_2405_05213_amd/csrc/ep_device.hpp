@@ -107,11 +107,11 @@ __device__ __forceinline__ T log_ratio(T x) {
   return ep_log1p(x) / x;
 }
 
-// J^{-2/3} for J = 1 + x > 0.  FP64: an FP32 estimate of y = J^{-1/3} refined by two Newton
-// steps on y^{-3} = J, y <- y (4 - J y^3) / 3, whose error squares at each step (2e-6 ->
-// 1e-11 -> rounding; 8e-16 relative over 0.05 <= J <= 20), instead of two FP64 library
-// transcendentals; outside 1e-30 < J < 1e30, beyond the FP32 estimate's range, and in FP32,
-// the logarithmic form exp(-2/3 ln(1 + x)).
+// J^{-2/3} for J = 1 + x > 0: an FP32 estimate of y = J^{-1/3} refined by Newton steps on
+// y^{-3} = J, y <- y (4 - J y^3) / 3, whose relative error squares at each step, instead of
+// two library transcendentals.  FP64: two steps (2e-6 -> 1e-11 -> rounding; 8e-16 relative
+// over 0.05 <= J <= 20); FP32: the hardware log2 / exp2 estimate and one step.  Outside
+// 1e-30 < J < 1e30, beyond the estimate's range, the logarithmic form exp(-2/3 ln(1 + x)).
 template <typename T>
 __device__ __forceinline__ T j_pow_m23(T J, T x) {
   if constexpr (sizeof(T) == 8) {
@@ -119,6 +119,12 @@ __device__ __forceinline__ T j_pow_m23(T J, T x) {
       double y = (double)exp2f(-log2f((float)J) * (1.0f / 3.0f));
       y = y * (4.0 - J * y * y * y) * (1.0 / 3.0);
       y = y * (4.0 - J * y * y * y) * (1.0 / 3.0);
+      return y * y;
+    }
+  } else {
+    if (J > 1e-30f && J < 1e30f) {
+      float y = __builtin_amdgcn_exp2f(-__builtin_amdgcn_logf(J) * (1.0f / 3.0f));
+      y = y * (4.0f - J * y * y * y) * (1.0f / 3.0f);
       return y * y;
     }
   }
