@@ -1,26 +1,28 @@
-"""Constitutive laws and the secant split of the internal force (ORACLE, test infrastructure).
+"""Constitutive laws and the H-matrix split of the internal force (ORACLE, test infrastructure).
 
 Everything here acts on arrays of 3x3 displacement gradients D = grad_X u with
 shape (..., 3, 3), D[..., i, k] = d u_i / d X_k, and F = I + D (Sec. 2.1,
 constitutive equation).
 
-The paper writes the internal force as R(u) = H(u) u (Sec. 2.3) and notes the
-split is neither obvious nor unique; Appendix A builds it for St. Venant-Kirchhoff
-and Yeoh solids by pulling one factor of the displacement gradient out of the
-stress, using the matrix P_e with det F - 1 = P_e : D (App. A, the det F - 1
-identity).  Here the same construction is written for the first Piola-Kirchhoff
-stress P = F S:
+The paper writes the internal force as R(u) = H(u) u (Sec. 2.3) and builds H(u) in
+App. A from the internal virtual work int dE : S dV = int grad w : (F S) dV,
+with S the second Piola-Kirchhoff stress.  Its H-matrix blocks H_AB (the 3x3 block
+between test node A and trial node B) are sums of terms of three shapes, which act
+on a field x with nodal values x_B, X = grad_X x = sum_B x_B (x) grad N_B, as
 
-    secant(D, X) is linear in X and secant(D, D) = P(F(D)),
+    (grad N_B . M . grad N_A) I        ->  X M            (M a 3x3 matrix)
+    L (grad N_B (x) grad N_A)          ->  L X^T
+    L (grad N_A (x) grad N_B) R^T      ->  (R : X) L,
 
-so that (H(u) x)_A = sum_e sum_q w_q detJ_q secant(D_q, grad x_q) . grad N_A(q)
-satisfies H(u) u = R(u) exactly.  For the Neo-Hookean and Yeoh solids it reads
+in the sense sum_B H_AB x_B = Phi(X) grad N_A summed over the quadrature.  So
 
-    secant(D, X) = a (X + G X^T) + (W : X) G,      G = F^{-T},
+    (H(u) x)_A = sum_e sum_q w_q detJ_q Phi(D_q, X_q) . grad N_A(q),
 
-with a, W scalar / matrix coefficients of the current D (given per model
-below); it uses F - F^{-T} = D + G D^T, I_1 - 3 = (2 I + D) : D and
-J - 1 = Q(D) : D.
+with Phi(D, X) = secant(D, X) below, term by term the printed H-matrix of App. A.
+Every such Phi splits as S_lin(D, X) + X S(D): the geometric part X S(D) (the terms
+that carry grad N_B . S . grad N_A) and the second Piola-Kirchhoff stress written
+linearly in X, S_lin(D, D) = S(D), so that secant(D, D) = F S = P and H(u) u = R(u).
+The matrix P_e of App. A (det F - 1 = P_e : D) is Qmat below.
 """
 from __future__ import annotations
 
@@ -170,35 +172,65 @@ class Material:
             return self.mu * (F - G) + (self.lam * lnJ)[..., None, None] * G
         return (I3 + D) @ self.pk2(D)
 
-    # -- secant split: secant(D, X) linear in X, secant(D, D) = pk1(D) ----------
-    def secant_coeffs(self, D):
-        """(a, G, W) with secant(D, X) = a (X + G X^T) + (W : X) G (NH / Yeoh)."""
+    # -- the H-matrix of App. A written as an operator on X = grad x -----------
+    def secant(self, D, X):
+        """Phi(D, X): linear in X, Phi(D, D) = P(F); H(u) x integrates Phi(D(u), grad x).
+
+        linear: sigma(X) (H = K, Sec. 5.2).
+        svk:    App. A, St. Venant-Kirchhoff H-matrix (the 1/2 of dE included):
+                  lambda/2 (dN_A (x) dN_B)(2I + D^T)  -> lambda ((I + D/2) : X) I
+                  mu (dN_B . dN_A) I                  -> mu X
+                  mu/2 (dN_B (x) dN_A)(2I + D^T)      -> mu (X^T + X^T D / 2)
+                  mu/2 D^T (dN_A . dN_B)              -> mu D^T X / 2
+                  (dN_B . S_SVK . dN_A) I             -> X S(D)
+        yeoh:   App. A, Yeoh H-matrix with the 1/2 of dE (the internal virtual work of the
+                Yeoh derivation) applied to each printed term; alpha = alpha_e,
+                beta = beta_e = 2 J / D1, Ci = C^{-1} = F^{-1} F^{-T}:
+                  2 alpha (dN_B . F^{-1} . dN_A) I          -> alpha X F^{-1}
+                  2 alpha F^{-T} (dN_B (x) dN_A)            -> alpha F^{-T} X^T
+                  -alpha (dN_B . Ci D^T . dN_A) I           -> -alpha/2 X Ci D^T
+                  -alpha D Ci (dN_B (x) dN_A)               -> -alpha/2 D Ci X^T
+                  -2/3 alpha Ci (dN_A (x) dN_B)(2I + D^T)   -> -alpha/3 ((2I + D) : X) Ci
+                  2 alpha (dN_B . [I - Ci tr C / 3] . dN_A) I -> alpha X (I - Ci tr C / 3)
+                  2 beta Ci (dN_A (x) dN_B) P_e^T           -> beta (P_e : X) Ci
+                  2 beta (J - 1) (dN_A . Ci . dN_B) I       -> beta (J - 1) X Ci
+                The first five terms and the P_e term give S_lin (at X = D they sum to
+                alpha (I - Ci tr C / 3) + beta (J - 1) Ci = S, using J - 1 = P_e : D and
+                D F^{-1} + F^{-T} D^T - D Ci D^T = I - Ci), the other two X S(D).
+        nh:     the same construction for the compressible Neo-Hookean solid ("trivially
+                extended", App. A): S = mu (I - Ci) + lambda ln J Ci, with mu in place of
+                alpha in the first four Yeoh terms, ln J = l(J) (J - 1), l(J) = ln J / (J - 1),
+                and lambda l(J) in place of beta in the P_e term, plus X S(D).
+        """
+        if self.model == "linear":
+            eps = 0.5 * (X + T(X))
+            return self.lam * tr(eps)[..., None, None] * I3 + 2.0 * self.mu * eps
+        S = self.pk2(D)
+        geo = X @ S                                         # (dN_B . S . dN_A) I terms
+        if self.model == "svk":
+            c = ddot(I3 + 0.5 * D, X)
+            return ((self.lam * c)[..., None, None] * I3
+                    + self.mu * (X + T(X) + 0.5 * (T(X) @ D + T(D) @ X)) + geo)
         F = I3 + D
-        G = np.linalg.inv(T(F))
+        Finv = np.linalg.inv(F)
+        FinvT = T(Finv)
+        Ci = Finv @ FinvT
         x = jm1(D)
-        Q = Qmat(D)
+        PX = ddot(Qmat(D), X)                               # P_e : X
         if self.model == "nh":
             a = np.full(D.shape[:-2], self.mu)
-            W = (self.lam * log_ratio(x))[..., None, None] * Q
+            vol = self.lam * log_ratio(x)                   # lambda ln J / (J - 1)
+            trterm = np.zeros(D.shape[:-2])
         elif self.model == "yeoh":
             J = 1.0 + x
             Jm23 = J ** (-2.0 / 3.0)
             z = ddot(F, F) * Jm23 - 3.0
-            a = 2.0 * Jm23 * (self.C10 + 2.0 * self.C20 * z + 3.0 * self.C30 * z ** 2)
-            beta = 2.0 / self.D1 * J
-            W = -(a / 3.0)[..., None, None] * (2.0 * I3 + D) + beta[..., None, None] * Q
+            a = 2.0 * Jm23 * (self.C10 + 2.0 * self.C20 * z + 3.0 * self.C30 * z ** 2)   # alpha_e
+            vol = 2.0 / self.D1 * J                                                       # beta_e
+            trterm = -(a / 3.0) * ddot(2.0 * I3 + D, X)
         else:
-            raise ValueError("secant_coeffs is defined for 'nh' and 'yeoh'")
-        return a, G, W
-
-    def secant(self, D, X):
-        if self.model == "linear":
-            eps = 0.5 * (X + T(X))
-            return self.lam * tr(eps)[..., None, None] * I3 + 2.0 * self.mu * eps
-        if self.model == "svk":
-            F = I3 + D
-            c = ddot(I3 + 0.5 * D, X)
-            return (self.lam * c)[..., None, None] * F + self.mu * F @ (X + T(X) @ F)
-        a, G, W = self.secant_coeffs(D)
-        return (a[..., None, None] * (X + G @ T(X))
-                + ddot(W, X)[..., None, None] * G)
+            raise ValueError(self.model)
+        a_ = a[..., None, None]
+        Slin = (a_ * (X @ Finv + FinvT @ T(X) - 0.5 * (X @ Ci @ T(D)) - 0.5 * (D @ Ci @ T(X)))
+                + (trterm + vol * PX)[..., None, None] * Ci)
+        return Slin + geo
