@@ -57,12 +57,17 @@ typedef enum {
  *               C20 = C30 = 0 is the decoupled Neo-Hookean solid (mu = 2 C10, kappa = 2/D1)
  *   EP_SVK    : {lambda, mu}                 St. Venant-Kirchhoff, S = lambda tr(E) I + 2 mu E,
  *               E = (F^T F - I) / 2, psi = lambda/2 (tr E)^2 + mu E : E
- * For EP_NH and EP_YEOH, H(u) is the secant operator with H(u) u = R(u) exactly,
- *   (H(u) x)_A = sum_e sum_q w detJ [a (X + G X^T) + (W : X) G] . grad N_A,
- *   X = grad x, G = F^{-T}, with a, W scalar / matrix coefficients of grad u built as in
- *   App. A (det F - 1 = P_e : grad u; I1 - 3 = (2 I + grad u) : grad u).  For EP_SVK the
- *   secant stress is lambda ((I + grad u / 2) : X) F + mu F (X + X^T F) (its value at X = grad u
- *   is P = F S). */
+ * H(u) is the H-matrix of App. A (R(u) = H(u) u exactly), applied matrix-free as
+ *   (H(u) x)_A = sum_e sum_q w detJ Phi(grad u, X) . grad N_A,   X = grad x,
+ * where Phi is the sum of App. A's printed blocks acting on X:
+ *   EP_SVK  (App. A, St. Venant-Kirchhoff H-matrix):
+ *     Phi = lambda ((I + D/2) : X) I + mu (X + X^T + (X^T D + D^T X)/2) + X S,  D = grad u;
+ *   EP_YEOH (App. A, Yeoh H-matrix, each printed term with the 1/2 of the internal virtual
+ *     work): Phi = alpha_e sym(X (F^{-1} + C^{-1})) + (W : X) C^{-1} + X S with
+ *     W = -(alpha_e/3)(2I + D) + beta_e P_e, P_e the matrix with det F - 1 = P_e : D;
+ *   EP_NH   (the same construction, App. A "trivially extended"): alpha_e -> mu,
+ *     W = lambda (ln J / (J - 1)) P_e;
+ * S is the model's second Piola-Kirchhoff stress at D and sym(Z) = (Z + Z^T)/2. */
 typedef enum { EP_LINEAR = 0, EP_NH = 1, EP_YEOH = 2, EP_SVK = 3 } ep_model;
 
 /* Arithmetic of the operator apply (stiffness matvec).  The Krylov recurrence, error
@@ -71,7 +76,7 @@ typedef enum { EP_LINEAR = 0, EP_NH = 1, EP_YEOH = 2, EP_SVK = 3 } ep_model;
  *   EP_PREC_MIXED_F32  : element kernels in FP32 with FP32 accumulation; converted at the
  *                        FP64 Krylov vector boundary.
  *   EP_PREC_MIXED_BF16 : element tangents (the element matrices of the operator's H, Sec. 2.3
- *                        with the secant split of App. A) formed once per projection with
+ *                        with the H-matrix of App. A) formed once per projection with
  *                        BF16 matrix-core products and FP32 accumulation, stored in BF16
  *                        (1152 bytes per element); every apply computes K_e x_e in FP32 with
  *                        FP32 accumulation.  Needs a congruent mesh (every element a
@@ -214,7 +219,7 @@ ep_status ep_get_step_log(ep_ctx* ctx, int n, int32_t* m_corr, int32_t* m_pred,
 
 /* y = H(u_lin) x on all 3*n_nodes DOFs (rows and columns of clamped DOFs included;
  * u_lin = NULL means u = 0, i.e. the linear-elastic stiffness).  x_dev, y_dev, u_lin_dev:
- * 3*n_nodes doubles.  Weak-form term 2 (Sec. 2.2) with the secant split (App. A).
+ * 3*n_nodes doubles.  Weak-form term 2 (Sec. 2.2) with the H-matrix of App. A.
  * Enqueued on the context's stream without waiting; an inverted element (secant
  * materials) is reported by the next ep_sync.  FP64 linear elasticity on a congruent mesh
  * runs as one node-by-node pass with the stored element stiffness. */

@@ -84,14 +84,30 @@ __device__ __forceinline__ void scatter_at(const QFactors<T>& Q, const T (&S)[3]
 }
 
 // ---------------------------------------------------------------------------------------
-// Constitutive coefficients of the secant split R(u) = H(u) u (App. A pattern):
-//   secant(D, X) = a (X + G X^T) + (W : X) G,   G = F^{-T}, F = I + D.
+// The H-matrix of App. A as an operator on X = grad x at one Gauss point.  App. A builds
+// H(u) from the internal virtual work int grad w : (F S) dV; its blocks H_AB act on x as
+//   Phi(D, X) = S_lin(D, X) + X S(D),     S_lin(D, D) = S(D)  (second Piola-Kirchhoff),
+// so that Phi(D, D) = F S and H(u) u = R(u).  For the Yeoh solid (App. A, last equation,
+// with the 1/2 of the internal virtual work) and the compressible Neo-Hookean solid built
+// the same way, the printed terms sum to
+//   Phi = a sym(X N) + (W : X) Ci + X S,   sym(Z) = (Z + Z^T) / 2,
+// with Ci = C^{-1} = F^{-1} F^{-T}, N = F^{-1} + Ci, S = Ci Sigma and
+//   Yeoh: a = alpha_e, W = -(a/3)(2I + D) + beta_e P_e, Sigma = a dev(E2) + beta_e (J-1) I
+//   NH:   a = mu,      W = lambda l(J) P_e,             Sigma = mu E2 + lambda ln J I
+// (E2 = C - I = D + D^T + D^T D, dev(E2) = E2 - tr(E2)/3 I, l(J) = ln J / (J - 1),
+// beta_e = 2 J / D1, P_e the matrix of App. A with J - 1 = P_e : D).  The first terms
+// are the printed F^{-1}, F^{-T}, C^{-1} D^T and D C^{-1} blocks (F^{-1} - C^{-1} D^T / 2
+// = N / 2), the (W : X) Ci term the (2I + D^T) and P_e^T blocks, X S the two blocks with
+// grad N_B . [..] . grad N_A.  S = Ci Sigma equals alpha (I - Ci tr C / 3) + beta (J-1) Ci
+// without the cancellation of I - Ci near D = 0.
 // ---------------------------------------------------------------------------------------
 template <typename T>
 struct Secant {
   T a;
-  T G[3][3];
+  T N[3][3];
   T W[3][3];
+  T S[3][3];
+  T Ci[6];      // symmetric: 00 11 22 01 12 02
 };
 
 __device__ __forceinline__ double ep_log1p(double x) { return log1p(x); }
@@ -131,7 +147,11 @@ __device__ __forceinline__ T j_pow_m23(T J, T x) {
   return ep_exp(T(-2.0 / 3.0) * ep_log1p(x));
 }
 
-// Returns false if J <= 0 (or not finite).
+__host__ __device__ constexpr int sym_idx(int i, int k) {
+  return i == k ? i : ((i + k == 1) ? 3 : ((i + k == 3) ? 4 : 5));
+}
+
+// Coefficients of Phi at D (Neo-Hookean or Yeoh).  Returns false if J <= 0 (or not finite).
 template <typename T, int MODEL>
 __device__ __forceinline__ bool secant_coeffs(const T (&D)[3][3], const double* mp, Secant<T>& s) {
   // polynomial cofactor of D
@@ -146,119 +166,158 @@ __device__ __forceinline__ bool secant_coeffs(const T (&D)[3][3], const double* 
   c[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
   c[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
   const T trD = D[0][0] + D[1][1] + D[2][2];
-  // Q = I + (trD I - D^T)/2 + cof(D)/3, with J - 1 = Q : D
-  T Qm[3][3];
+  // P_e = I + (trD I - D^T)/2 + cof(D)/3 (App. A), J - 1 = P_e : D; kept in W for now
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      Qm[i][k] = (i == k ? T(1) + T(0.5) * trD : T(0)) - T(0.5) * D[k][i] + c[i][k] * T(1.0 / 3.0);
+      s.W[i][k] = (i == k ? T(1) + T(0.5) * trD : T(0)) - T(0.5) * D[k][i] + c[i][k] * T(1.0 / 3.0);
   T x = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) x += Qm[i][k] * D[i][k];
+    for (int k = 0; k < 3; ++k) x += s.W[i][k] * D[i][k];
   const T J = T(1) + x;
   if (!(J > T(0))) return false;
-  // G = F^{-T} = cof(F) / J; cof(I + D) = cof(D) + (trD I - D^T) + I
+  // F^{-1} = cof(F)^T / J with cof(I + D) = cof(D) + (trD I - D^T) + I; N = F^{-1} for now
   const T Jinv = T(1) / J;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-      s.G[i][k] = (c[i][k] + (i == k ? T(1) + trD : T(0)) - D[k][i]) * Jinv;
+      s.N[i][k] = (c[k][i] + (i == k ? T(1) + trD : T(0)) - D[i][k]) * Jinv;
+  // Ci = F^{-1} F^{-T}
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = i; k < 3; ++k)
+      s.Ci[sym_idx(i, k)] = s.N[i][0] * s.N[k][0] + s.N[i][1] * s.N[k][1] + s.N[i][2] * s.N[k][2];
+  // E2 = D + D^T + D^T D (symmetric)
+  T E2[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = i; k < 3; ++k)
+      E2[sym_idx(i, k)] = D[i][k] + D[k][i] + D[0][i] * D[0][k] + D[1][i] * D[1][k] + D[2][i] * D[2][k];
+  T Sg[6];   // Sigma
+  T a;
   if (MODEL == kNH) {
     const T mu = T(mp[0]), lam = T(mp[1]);
-    s.a = mu;
-    const T f = lam * log_ratio(x);
+    a = mu;
+    const T l = log_ratio(x);
+    const T vol = lam * l * x;      // lambda ln J
+#pragma unroll
+    for (int t = 0; t < 6; ++t) Sg[t] = mu * E2[t] + (t < 3 ? vol : T(0));
+    const T f = lam * l;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) s.W[i][k] = f * Qm[i][k];
+      for (int k = 0; k < 3; ++k) s.W[i][k] *= f;
   } else {   // Yeoh
     const T C10 = T(mp[0]), C20 = T(mp[1]), C30 = T(mp[2]), D1 = T(mp[3]);
     const T Jm23 = j_pow_m23(J, x);
-    T I1 = T(0);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const T Fik = D[i][k] + (i == k ? T(1) : T(0));
-        I1 += Fik * Fik;
-      }
-    const T z = I1 * Jm23 - T(3);
-    const T a = T(2) * Jm23 * (C10 + T(2) * C20 * z + T(3) * C30 * z * z);
+    const T trE2 = E2[0] + E2[1] + E2[2];
+    const T z = (T(3) + trE2) * Jm23 - T(3);     // I1bar - 3, tr C = 3 + tr E2
+    a = T(2) * Jm23 * (C10 + T(2) * C20 * z + T(3) * C30 * z * z);
     const T beta = T(2) / D1 * J;
-    s.a = a;
+    const T bj = beta * x;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) Sg[t] = a * E2[t] + (t < 3 ? bj - a * trE2 * T(1.0 / 3.0) : T(0));
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        s.W[i][k] = -(a * T(1.0 / 3.0)) * ((i == k ? T(2) : T(0)) + D[i][k]) + beta * Qm[i][k];
+        s.W[i][k] = -(a * T(1.0 / 3.0)) * ((i == k ? T(2) : T(0)) + D[i][k]) + beta * s.W[i][k];
   }
+  s.a = a;
+  // S = Ci Sigma
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      s.S[i][k] = s.Ci[sym_idx(i, 0)] * Sg[sym_idx(0, k)] + s.Ci[sym_idx(i, 1)] * Sg[sym_idx(1, k)] +
+                  s.Ci[sym_idx(i, 2)] * Sg[sym_idx(2, k)];
+  // N = F^{-1} + Ci
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.N[i][k] += s.Ci[sym_idx(i, k)];
   return true;
 }
 
-// S += w * [a (X + G X^T) + (W : X) G]
+// P += w * [a sym(X N) + (W : X) Ci + X S]
 template <typename T>
-__device__ __forceinline__ void secant_apply(const Secant<T>& s, T w, const T (&X)[3][3], T (&S)[3][3]) {
+__device__ __forceinline__ void secant_apply(const Secant<T>& s, T w, const T (&X)[3][3], T (&P)[3][3]) {
   T wx = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) wx += s.W[i][k] * X[i][k];
-  const T aw = w * s.a, bw = w * wx;
+  T Z[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Z[i][k] = X[i][0] * s.N[0][k] + X[i][1] * s.N[1][k] + X[i][2] * s.N[2][k];
+  const T ah = T(0.5) * w * s.a, bw = w * wx;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const T gxt = s.G[i][0] * X[k][0] + s.G[i][1] * X[k][1] + s.G[i][2] * X[k][2];
-      S[i][k] += aw * (X[i][k] + gxt) + bw * s.G[i][k];
+      const T xs = X[i][0] * s.S[0][k] + X[i][1] * s.S[1][k] + X[i][2] * s.S[2][k];
+      P[i][k] += ah * (Z[i][k] + Z[k][i]) + bw * s.Ci[sym_idx(i, k)] + w * xs;
     }
 }
 
-// St. Venant-Kirchhoff (App. A): S = lambda tr(E) I + 2 mu E with E = (F^T F - I) / 2.  The
-// first Piola-Kirchhoff stress P = F S written linearly in X = grad x:
-//   secant(D, X) = lambda ((I + D/2) : X) F + mu F (X + X^T F),
-// since (I + D/2) : D = tr E and D + D^T F = 2 E, so secant(D, D) = P and H(u) u = R(u).
-// The set keeps F and I + D/2.
+// St. Venant-Kirchhoff (App. A, its H-matrix with the leading 1/2): the printed blocks act
+// on X = grad x as
+//   lambda ((I + D/2) : X) I + mu (X + X^T + (X^T D + D^T X) / 2) + X S,
+// S = lambda tr(E) I + 2 mu E = (lambda tr(E2) / 2) I + mu E2 (the nodal sum S_SVK,e).
+// Written as lambda (Hh : X) I + mu sym(B X) + X S with Hh = I + D/2, B = 2I + D^T.
 template <typename T>
 struct SecantSVK {
-  T F[3][3];
   T Hh[3][3];
+  T S[6];       // symmetric: 00 11 22 01 12 02
 };
 
 template <typename T>
-__device__ __forceinline__ void svk_coeffs(const T (&D)[3][3], SecantSVK<T>& s) {
+__device__ __forceinline__ void svk_coeffs(const T (&D)[3][3], T lam, T mu, SecantSVK<T>& s) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      s.F[i][k] = D[i][k] + (i == k ? T(1) : T(0));
-      s.Hh[i][k] = T(0.5) * D[i][k] + (i == k ? T(1) : T(0));
-    }
+    for (int k = 0; k < 3; ++k) s.Hh[i][k] = T(0.5) * D[i][k] + (i == k ? T(1) : T(0));
+  T E2[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = i; k < 3; ++k)
+      E2[sym_idx(i, k)] = D[i][k] + D[k][i] + D[0][i] * D[0][k] + D[1][i] * D[1][k] + D[2][i] * D[2][k];
+  const T lt = T(0.5) * lam * (E2[0] + E2[1] + E2[2]);
+#pragma unroll
+  for (int t = 0; t < 6; ++t) s.S[t] = mu * E2[t] + (t < 3 ? lt : T(0));
 }
 
-// S += w * [lambda (Hh : X) F + mu F (X + X^T F)]
+// P += w * [lambda (Hh : X) I + mu sym(B X) + X S], B = 2 Hh^T (= 2I + D^T)
 template <typename T>
 __device__ __forceinline__ void svk_apply(const SecantSVK<T>& s, T lam, T mu, T w, const T (&X)[3][3],
-                                          T (&S)[3][3]) {
+                                          T (&P)[3][3]) {
   T c = T(0);
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int k = 0; k < 3; ++k) c += s.Hh[i][k] * X[i][k];
-  T Y[3][3];   // X + X^T F
+  T Y[3][3];   // Hh^T X = B X / 2
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) Y[i][k] = X[i][k] + X[0][i] * s.F[0][k] + X[1][i] * s.F[1][k] + X[2][i] * s.F[2][k];
+    for (int k = 0; k < 3; ++k) Y[i][k] = s.Hh[0][i] * X[0][k] + s.Hh[1][i] * X[1][k] + s.Hh[2][i] * X[2][k];
   const T lc = w * lam * c, wm = w * mu;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
-      S[i][k] += lc * s.F[i][k] + wm * (s.F[i][0] * Y[0][k] + s.F[i][1] * Y[1][k] + s.F[i][2] * Y[2][k]);
+    for (int k = 0; k < 3; ++k) {
+      const T xs = X[i][0] * s.S[sym_idx(0, k)] + X[i][1] * s.S[sym_idx(1, k)] + X[i][2] * s.S[sym_idx(2, k)];
+      P[i][k] += (i == k ? lc : T(0)) + wm * (Y[i][k] + Y[k][i]) + w * xs;
+    }
 }
 
 // Lame constants of the linear material (E, nu) or of the rest-state tangent.
@@ -360,11 +419,11 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
         T Du[3][3];
         SecantSVK<T> sv;
         grad_at(Q, u0, Jinv, Du);
-        svk_coeffs(Du, sv);
+        svk_coeffs(Du, lam, mu, sv);
         svk_apply(sv, lam, mu, T(op.wts[0]), X, S);
         if (nsets >= 2) {
           grad_at(Q, u1, Jinv, Du);
-          svk_coeffs(Du, sv);
+          svk_coeffs(Du, lam, mu, sv);
           svk_apply(sv, lam, mu, T(op.wts[1]), X, S);
         }
       } else if (MODEL != kLinear) {
@@ -478,7 +537,7 @@ __device__ __forceinline__ bool elem_force_qp(const Mesh& M, const OpArgs& op, i
         T Du[3][3];
         SecantSVK<T> sv;
         grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
-        svk_coeffs(Du, sv);
+        svk_coeffs(Du, T(lam_d), T(mu_d), sv);
         svk_apply(sv, T(lam_d), T(mu_d), T(op.wts[s]), X, S);
       }
     } else if (MODEL != kLinear) {

@@ -1,5 +1,7 @@
 // Formation of the stored BF16 element tangents (see ep_tangent.hpp) and the stand-alone
 // operator apply that uses them.
+#include <type_traits>
+
 #include "ep_kernels.hpp"
 #include "ep_tangent.hpp"
 
@@ -57,8 +59,17 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
   bool ok = true;
   const int nsets = (MODEL == kLinear || e >= M.n_elems) ? 0 : op.nsets;
   const float wdet = e < M.n_elems ? M.geo32[(size_t)q * 10 + 9] : 0.f;
-  Secant<float> sc[2] = {};          // zero coefficients for an absent set (weight 0)
+  // coefficient sets of the operator (zero for an absent set, whose weight is 0)
+  using SetT = typename std::conditional<MODEL == kSVK, SecantSVK<float>, Secant<float>>::type;
+  SetT sc[2] = {};
   float wsv[2] = {0.f, 0.f};
+  float lam_u = 0.f, mu_u = 0.f;   // rest-state (linear) / St. Venant-Kirchhoff moduli
+  if (e < M.n_elems) {
+    double lam_d, mu_d;
+    rest_lame(M.model, M.mp, lam_d, mu_d);
+    lam_u = float(lam_d);
+    mu_u = float(mu_d);
+  }
   if (nsets > 0) {                 // uniform over the element's 8 lanes
     const QFactors<float> Q(q);
     float Jinv[9];
@@ -80,32 +91,13 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
         }
         float Du[3][3];
         grad_at(Q, ue, Jinv, Du);
-        if constexpr (MODEL == kSVK) {
-          // St. Venant-Kirchhoff: F in G, I + D/2 in W
-          SecantSVK<float> sv;
-          svk_coeffs(Du, sv);
-#pragma unroll
-          for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              sc[s].G[a][b] = sv.F[a][b];
-              sc[s].W[a][b] = sv.Hh[a][b];
-            }
-        } else {
-          ok &= secant_coeffs<float, MODEL>(Du, M.mp, sc[s]);
-        }
+        if constexpr (MODEL == kSVK) svk_coeffs(Du, lam_u, mu_u, sc[s]);
+        else ok &= secant_coeffs<float, MODEL>(Du, M.mp, sc[s]);
         wsv[s] = float(op.wts[s]) * wdet;
       }
     }
   }
   if (!ok) atomicCAS(err, 0, kErrInverted);
-  float lam_u = 0.f, mu_u = 0.f;   // rest-state (linear) / St. Venant-Kirchhoff moduli
-  if (e < M.n_elems) {
-    double lam_d, mu_d;
-    rest_lame(M.model, M.mp, lam_d, mu_d);
-    lam_u = float(lam_d);
-    mu_u = float(mu_d);
-  }
   const float lam = lam_u * wdet, mu = mu_u * wdet;
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -124,15 +116,18 @@ __global__ __launch_bounds__(kTanThreads) void k_form_tangent(Mesh M, OpArgs op,
             c = 0.f;
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
+              // c = d Phi_ij / d X_kl of the operator at this point, unscaled by w det J
               float t;
               if constexpr (MODEL == kSVK) {
-                // d/dX_kl of lambda (Hh : X) F + mu (F X + F X^T F), unscaled by w det J
-                t = lam_u * sc[s].G[i][j] * sc[s].W[k][l] +
-                    mu_u * ((j == l ? sc[s].G[i][k] : 0.f) + sc[s].G[i][l] * sc[s].G[k][j]);
+                // lambda (Hh : X) I + mu (Hh^T X + X^T Hh) + X S
+                t = (i == j ? lam_u * sc[s].Hh[k][l] : 0.f) +
+                    mu_u * ((j == l ? sc[s].Hh[k][i] : 0.f) + (i == l ? sc[s].Hh[k][j] : 0.f)) +
+                    (i == k ? sc[s].S[sym_idx(l, j)] : 0.f);
               } else {
-                t = sc[s].G[i][j] * sc[s].W[k][l];
-                if (i == k && j == l) t += sc[s].a;
-                if (j == k) t += sc[s].a * sc[s].G[i][l];
+                // a sym(X N) + (W : X) Ci + X S
+                t = sc[s].W[k][l] * sc[s].Ci[sym_idx(i, j)];
+                if (i == k) t += 0.5f * sc[s].a * sc[s].N[l][j] + sc[s].S[l][j];
+                if (j == k) t += 0.5f * sc[s].a * sc[s].N[l][i];
               }
               c += wsv[s] * t;          // wsv = 0 for an absent set
             }

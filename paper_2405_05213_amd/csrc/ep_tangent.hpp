@@ -1,9 +1,11 @@
 // Stored element tangents in BF16 (precision mode EP_PREC_MIXED_BF16).
 //
-// The operator's element matrix (Sec. 2.3 with the secant split of App. A) is
+// The operator's element matrix (Sec. 2.3 with the H-matrix of App. A) is
 //   K_e[(A,i),(B,k)] = sum_q sum_{j,l} dN_A/dX_j(q) dN_B/dX_l(q) C_q[(i,j),(k,l)],
-//   C_q[(i,j),(k,l)] = w_q det J_q sum_s w_s [a_s (d_ik d_jl + G_s,il d_jk) + G_s,ij W_s,kl],
-// the derivative of the secant stress a (X + G X^T) + (W : X) G with respect to X = grad x,
+//   C_q[(i,j),(k,l)] = w_q det J_q sum_s w_s dPhi_s,ij / dX_kl,
+// the derivative of the per-point operator Phi (linear in X = grad x; for the Neo-Hookean
+// and Yeoh solids a sym(X N) + (W : X) Ci + X S, for St. Venant-Kirchhoff
+// lambda (Hh : X) I + mu (Hh^T X + X^T Hh) + X S; ep_device.hpp),
 // summed over the operator's coefficient sets s (predictor: 1.75 and -0.75; corrector: 1;
 // rest state: C = mu (d_ik d_jl + d_il d_jk) + lambda d_ij d_kl).  On a congruent mesh the
 // gradients dN/dX are the same for every element, so all element matrices come from one
