@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import sys
 
 import numpy as np
 
@@ -125,11 +126,25 @@ class Context:
         if stream is not None:
             self._call("ep_set_stream", C.c_void_p(stream))
 
-    def __del__(self):
+    def close(self):
+        """Release the context (its HIP graphs and host state) now."""
         h = getattr(self, "h", None)
         if h is not None and getattr(self, "_L", None) is not None:
             self._L.ep_destroy(h)
-            self.h = None
+        self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        # during interpreter shutdown the HIP runtime (and a profiler attached to it) may
+        # already be finalised: destroying graphs then is unsafe, and the process is ending
+        if sys.is_finalizing():
+            return
+        self.close()
 
     def _call(self, name, *args):
         rc = getattr(self._L, name)(self.h, *args)
