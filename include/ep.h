@@ -244,6 +244,21 @@ ep_status ep_vector_length(ep_ctx* ctx, int64_t* length, int64_t* padded_length)
  * (Sec. 4.3).  Host arrays. */
 ep_status ep_expm(ep_ctx* ctx, int m, const double* H_host, double* E_host);
 
+/* Allocation-free variant of ep_expm, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): E = exp(H)
+ * for a dense m x m row-major FP64 matrix in device memory of the current HIP device, the
+ * same kernel and result as ep_expm.  No context is needed.
+ *   m:          1 <= m <= 256, else EP_ERR_ARG (the scratch is sized for m = 256);
+ *   H_dev:      m*m doubles, read only; E_dev: m*m doubles, written (must not overlap H_dev);
+ *   hip_stream: stream of the current device (NULL: the null stream); enqueued without
+ *               waiting.
+ * Scratch: up to 6 m (m+1) doubles (3,158,016 bytes at m = 256) in a library-owned device
+ * array, one per GPU, held until the process ends; no hipMalloc/hipFree or allocating
+ * library call is made.  Every call on a GPU shares that GPU's array, so calls that overlap
+ * on one GPU (different streams, or host threads) race: order them on one stream.
+ * EP_ERR_HIP if the scratch address cannot be resolved or the launch fails. */
+ep_status ep_expm_noalloc(int m, const double* H_dev, double* E_dev, void* hip_stream);
+
 /* m Arnoldi steps with modified Gram-Schmidt (Sec. 4.3) on tau * A (as ep_apply_A) from
  * w_dev.  Writes V (m+1 rows of padded_length doubles, device) and the Hessenberg
  * Htilde ((m+1) x m row-major, host).  Returns the number of completed steps in

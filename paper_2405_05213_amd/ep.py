@@ -63,6 +63,7 @@ _SIGS = {
     "ep_apply_A": [_vp, _vp, _dbl, _dbl, _vp, _vp],
     "ep_vector_length": [_vp, _P(_i64), _P(_i64)],
     "ep_expm": [_vp, C.c_int, _vp, _vp],
+    "ep_expm_noalloc": [C.c_int, _vp, _vp, _vp],
     "ep_arnoldi": [_vp, _vp, _dbl, _dbl, _vp, C.c_int, _vp, _vp, _P(C.c_int)],
     "ep_expv": [_vp, _vp, _dbl, _dbl, _vp, _vp, _P(C.c_int), _P(C.c_int), _P(_dbl)],
     "ep_batch_add_instance": [_vp, _i64, _vp, _i64, _vp, C.c_int, _vp, C.c_int, _dbl, _i64, _vp, _i64, _vp,
@@ -294,6 +295,14 @@ class Context:
         self._call("ep_expv", _ptr(u_lin), float(tau), float(pscale), _ptr(w), _ptr(y), C.byref(m), C.byref(k),
                    C.byref(e))
         return m.value, k.value, e.value
+
+
+def expm_noalloc(m, H_dev, E_dev, stream=None):
+    """ep_expm_noalloc: E = exp(H) on device tensors (m x m FP64, row-major) of the current
+    device, enqueued on `stream` (a raw HIP stream handle; None = null stream)."""
+    rc = lib().ep_expm_noalloc(int(m), _ptr(H_dev), _ptr(E_dev), C.c_void_p(stream) if stream else None)
+    if rc != EP_OK:
+        raise EPError(rc, "ep_expm_noalloc failed")
 
 
 class Batch(Context):
