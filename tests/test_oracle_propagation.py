@@ -180,3 +180,53 @@ def test_small_load_limit_is_linear():
         diffs.append(_rel(a.u(), b.u()))
     assert diffs[1] < diffs[0] / 5.0
     assert diffs[1] < 1e-3
+
+
+def _spy_predictor(pr):
+    """Record (weights and linearisation points, load time, duration, step start) of every
+    predictor propagation the stepper makes."""
+    rec = []
+    orig = pr.propagate
+
+    def spy(w, tau, t_eval, hspec, kind):
+        if kind == "pred":
+            rec.append(dict(hspec=[(wt, np.array(U)) for wt, U in hspec], t_eval=t_eval, tau=tau, t=pr.t))
+        return orig(w, tau, t_eval, hspec, kind)
+
+    pr.propagate = spy
+    return rec
+
+
+@pytest.mark.slow
+def test_predictor_extrapolates_H_to_the_quarter_step():
+    """Sec. 4.2: the predictor propagates w_{n-1} by dt/2 with H extrapolated linearly from the
+    two previous midpoints to t_{n-1} + dt/4, with the load taken at that time.  Against a
+    fine-step reference u(t): the predicted operator sum_i w_i H(u_i) x must approach
+    H(u(t_{n-1} + dt/4)) x as O(dt^2); a constant predictor or extrapolation to another time
+    gives O(dt)."""
+    T = 0.006                                    # start of the step whose predictor is checked
+    prob = lambda dt: _nh_bar(dt, T + dt, load=4e4).with_(knots_t=np.array([0.0, 0.02]),
+                                                          knots_s=np.array([0.0, 1.0]))
+    ks = (4, 8, 16, 32)
+    dt_ref = T / (8 * ks[-1])
+    ref = Propagator(prob(dt_ref), tol=1e-13, m_max=64)
+    u_ref = {0: ref.u()}
+    for i in range(1, int(round((T + T / (4 * ks[0])) / dt_ref)) + 1):
+        ref.step(dt_ref)
+        u_ref[i] = ref.u()
+    x = np.random.default_rng(41).normal(size=ref.n3)
+    errs = []
+    for k in ks:
+        dt = T / k
+        pr = Propagator(prob(dt), tol=1e-13, m_max=64)
+        rec = _spy_predictor(pr)
+        pr.run(dt, k + 1)
+        last = rec[-1]
+        assert abs(last["t"] - T) < 1e-12 * T
+        assert abs(last["tau"] - 0.5 * dt) < 1e-15 and abs(last["t_eval"] - (T + 0.25 * dt)) < 1e-15
+        assert len(last["hspec"]) == 2 and abs(sum(w for w, _ in last["hspec"]) - 1.0) < 1e-15
+        Hp = sum(w * pr.fem.H_apply(U, x) for w, U in last["hspec"])
+        Href = pr.fem.H_apply(u_ref[int(round((T + 0.25 * dt) / dt_ref))], x)
+        errs.append(np.linalg.norm(Hp - Href) / np.linalg.norm(Href))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 1.7), (errs, orders)
