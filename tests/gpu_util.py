@@ -53,4 +53,12 @@ def yeoh_rubber_of(prob):
 
 
 def rel(a, b):
+    """Relative error in the 2-norm (reported beside the element-wise error)."""
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxrel(a, b, scale=None):
+    """Element-wise error max_i |a_i - b_i| / max_i |b_i| (or / scale)."""
+    a, b = np.asarray(a), np.asarray(b)
+    s = np.abs(b).max() if scale is None else scale
+    return float(np.abs(a - b).max() / max(s, 1e-300))

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from workloads import config, distort
-from tests.gpu_util import pair, rel, say, svk_of
+from tests.gpu_util import pair, maxrel, say, svk_of
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -47,7 +47,7 @@ def test_apply_H_bf16(model, name, over, amp):
     y = torch.zeros(n3, dtype=torch.float64, device=DEV)
     ctx.apply_H(None if u is None else _t(u), _t(x), y)
     ref = orc.fem.H_apply(u, x)
-    err = rel(y.cpu().numpy(), ref)
+    err = maxrel(y.cpu().numpy(), ref)
     say(f"  rel err {err:.2e}")
     assert err < TOL_OP
 
@@ -64,11 +64,11 @@ def test_apply_H_bf16_tangents_follow_the_state():
     u = 0.02 * rng.normal(size=n3) * (p.xyz.max() - p.xyz.min())
     y = torch.zeros(n3, dtype=torch.float64, device=DEV)
     ctx.apply_H(_t(u), _t(x), y)
-    assert rel(y.cpu().numpy(), orc.fem.H_apply(u, x)) < TOL_OP
+    assert maxrel(y.cpu().numpy(), orc.fem.H_apply(u, x)) < TOL_OP
     ctx.apply_H(None, _t(x), y)
-    assert rel(y.cpu().numpy(), orc.fem.H_apply(np.zeros(n3), x)) < TOL_OP
+    assert maxrel(y.cpu().numpy(), orc.fem.H_apply(np.zeros(n3), x)) < TOL_OP
     ctx.apply_H(_t(u), _t(x), y)
-    assert rel(y.cpu().numpy(), orc.fem.H_apply(u, x)) < TOL_OP
+    assert maxrel(y.cpu().numpy(), orc.fem.H_apply(u, x)) < TOL_OP
 
 
 @pytest.mark.parametrize("model,name,over", [("nh", "c3", dict(nx=8, ny=2, nz=2, dt=5e-4)),
@@ -84,7 +84,7 @@ def test_steps_bf16(model, name, over, ortho):
     ctx.step(p.dt, n)
     t, u, v = ctx.get_state()
     orc.run(p.dt, n)
-    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
     say(f"  rel err u {eu:.2e} v {ev:.2e}")
     assert eu < TOL_TRAJ and ev < TOL_TRAJ
 

@@ -8,7 +8,7 @@ import pytest
 
 from workloads import config
 from oracle.stepper import Propagator
-from tests.gpu_util import pair, rel, say
+from tests.gpu_util import pair, maxrel, say
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -30,7 +30,7 @@ def test_c2_full_step(prec, tol_u, tol_v):
     ctx.step(p.dt, 1)
     t, u, v = ctx.get_state()
     orc.step(p.dt)
-    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
     say(f"  rel err u {eu:.2e} v {ev:.2e}")
     assert eu < tol_u and ev < tol_v
 
@@ -45,7 +45,7 @@ def test_c3_full_step(prec, tol):
     ctx.step(p.dt, 1)
     t, u, v = ctx.get_state()
     orc.step(p.dt)
-    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
     say(f"  rel err u {eu:.2e} v {ev:.2e}")
     assert eu < tol and ev < tol
     if prec == "f64":
@@ -67,7 +67,7 @@ def test_c4_full_operator_and_energy(prec, tol):
     y = torch.zeros(n3, dtype=torch.float64, device=DEV)
     ctx.apply_H(_t(u), _t(x), y)
     ref = orc.fem.H_apply(u, x)
-    assert rel(y.cpu().numpy()[orc.free], ref[orc.free]) < tol
+    assert maxrel(y.cpu().numpy()[orc.free], ref[orc.free]) < tol
     # energies of a deformed, moving state
     v = np.zeros(n3)
     v[orc.free] = 1e-3 * rng.normal(size=orc.N)
@@ -90,7 +90,7 @@ def test_lattice_apply_many_tiles():
     x = np.random.default_rng(22).normal(size=3 * p.n_nodes)
     y = torch.zeros(3 * p.n_nodes, dtype=torch.float64, device=DEV)
     ctx.apply_H(None, _t(x), y)
-    err = rel(y.cpu().numpy(), orc.fem.H_apply(None, x))
+    err = maxrel(y.cpu().numpy(), orc.fem.H_apply(None, x))
     say(f"  rel err {err:.2e}")
     assert err < 1e-12
 
@@ -113,6 +113,56 @@ def test_c5_full_batch_sampled(prec, tol):
         t, u, v = b.get_state(i)
         orc = Propagator(p, m_max=32)
         orc.run(p.dt, n)
-        eu, ev = rel(u, orc.u()), rel(v, orc.v())
+        eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
         say(f"  instance {i} ({p.n_nodes} nodes): rel err u {eu:.2e} v {ev:.2e}")
         assert eu < tol and ev < tol
+
+
+# ---------------------------------------------------------------------------------------
+# Several steps at full size against stored oracle results (tests/golden/fullsize_*.json,
+# written by tests/golden/make_fullsize_golden.py, which runs only the oracle): a seeded
+# sample of 2048 free DOFs of u and v, element-wise error normalised by max |u|, max |v| of
+# the oracle over all DOFs, plus the energies and, in FP64, the subspace sizes.
+# ---------------------------------------------------------------------------------------
+def _golden(case):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"fullsize_{case}.json")) as fh:
+        return json.load(fh)
+
+
+# (case, precision, tol u, tol v, tol energy)
+GOLDEN_CASES = [
+    ("c2dt1e-3", "f64", 1e-8, 1e-8, 1e-8),        # one step at dt = 1e-3: m = 56, 32 substeps
+    ("c2dt1e-3", "mixed_f32", 1e-4, 1e-3, 1e-5),
+    ("c3", "f64", 1e-8, 1e-8, 1e-8),              # three steps: the two-point predictor runs
+    ("c3", "mixed_f32", 1e-6, 1e-6, 1e-6),
+    ("c4", "f64", 1e-8, 1e-8, 1e-8),              # three steps of the 64^3 Yeoh block
+    ("c4", "mixed_f32", 1e-6, 1e-6, 1e-6),
+]
+
+
+@pytest.mark.parametrize("case,prec,tol_u,tol_v,tol_e", GOLDEN_CASES)
+def test_fullsize_steps_against_stored_oracle(case, prec, tol_u, tol_v, tol_e):
+    from paper_2405_05213_amd import solver_from_problem
+    g = _golden(case)
+    say(f"[full] {case} {g['steps']} steps {prec} {g['krylov']}")
+    p = config(g["workload"], **g["overrides"])
+    ctx = solver_from_problem(p, precision=prec, **g["krylov"])
+    ctx.step(p.dt, g["steps"])
+    t, u, v = ctx.get_state()
+    idx = np.asarray(g["dofs"])
+    eu = maxrel(u[idx], np.asarray(g["u"]), g["max_abs_u"])
+    ev = maxrel(v[idx], np.asarray(g["v"]), g["max_abs_v"])
+    ke, se, we = ctx.energy()
+    ko, so, wo = g["energies"]
+    ee = abs((ke + se - we) - (ko + so - wo)) / (ko + so)
+    say(f"  element-wise err u {eu:.2e} v {ev:.2e}, energy {ee:.2e}")
+    assert abs(t - g["t"]) < 1e-15
+    assert eu < tol_u and ev < tol_v and ee < tol_e
+    if prec == "f64":
+        log = ctx.step_log(g["steps"])
+        assert list(log["m_corr"]) == g["m_corr"] and list(log["k_corr"]) == g["k_corr"]
+        if g["m_pred"]:
+            assert list(log["m_pred"]) == g["m_pred"]
+    ctx.close()

@@ -4,7 +4,7 @@ import pytest
 
 from workloads import config, distort
 from oracle import krylov
-from tests.gpu_util import from_gpu_vec, pair, rel, say, svk_of, to_gpu_vec, yeoh_rubber_of
+from tests.gpu_util import from_gpu_vec, pair, maxrel, say, svk_of, to_gpu_vec, yeoh_rubber_of
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -59,7 +59,7 @@ def test_apply_H_matches_oracle(model, name, over, distorted, prec):
     ctx.apply_H(None if u is None else _t(u), _t(x), y)
     ref = orc.fem.H_apply(u, x)
     tol = 1e-12 if prec == "f64" else 2e-6
-    assert rel(_np(y), ref) < tol
+    assert maxrel(_np(y), ref) < tol
 
 
 @pytest.mark.parametrize("m,scale", [(1, 0.3), (6, 0.9), (12, 3.0), (30, 40.0), (48, 1000.0), (64, 250.0), (128, 900.0),
@@ -127,7 +127,7 @@ def test_arnoldi_matches_oracle(name, over, workgroups, ortho):
     assert np.abs(H - Ho).max() <= 1e-9 * scale
     Vg = _np(V).reshape(m + 1, Lp)
     for j in (0, 1, 5, m):
-        assert rel(from_gpu_vec(orc, Vg[j]), Vo[j]) < 1e-8
+        assert maxrel(from_gpu_vec(orc, Vg[j]), Vo[j]) < 1e-8
 
 
 @pytest.mark.parametrize("ortho", [0, 1])
@@ -145,7 +145,7 @@ def test_expv_matches_oracle(dt, workgroups, ortho):
     yo, info = krylov.expv(lambda v, f: orc.A_apply(v, f, None, orc.P0bar), w, dt, tol=p.tol, m_max=48,
                            check_every=4, state={})
     assert k == info["k"] and m == info["m"][-1]
-    assert rel(from_gpu_vec(orc, _np(y)), yo) < 1e-9
+    assert maxrel(from_gpu_vec(orc, _np(y)), yo) < 1e-9
 
 
 @pytest.mark.parametrize("ortho", [0, 1])
@@ -161,8 +161,8 @@ def test_linear_steps_c1(mode, ortho):
     t, u, v = ctx.get_state()
     orc.run(p.dt, p.n_steps)
     assert abs(t - orc.t) < 1e-15
-    assert rel(u, orc.u()) < 1e-8
-    assert rel(v, orc.v()) < 1e-8
+    assert maxrel(u, orc.u()) < 1e-8
+    assert maxrel(v, orc.v()) < 1e-8
     ke, se, we = ctx.energy()
     ko, so_, wo = orc.energies()
     assert abs(ke - ko) <= 1e-8 * (ko + so_) and abs(se - so_) <= 1e-8 * (ko + so_)
@@ -195,8 +195,8 @@ def test_nonlinear_steps(model, name, over, mode, ortho):
     ctx.step(p.dt, n)
     t, u, v = ctx.get_state()
     orc.run(p.dt, n)
-    assert rel(u, orc.u()) < 1e-8
-    assert rel(v, orc.v()) < 1e-8
+    assert maxrel(u, orc.u()) < 1e-8
+    assert maxrel(v, orc.v()) < 1e-8
     ke, se, we = ctx.energy()
     ko, so_, wo = orc.energies()
     assert abs(se - so_) <= 1e-8 * (ko + so_ + abs(wo))
@@ -267,8 +267,8 @@ def test_slices_in_device_memory(ortho):
     orc.run(p.dt, n)
     _, u, v = ctx.get_state()
     _, ur, vr = ref.get_state()
-    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
-    assert rel(u, ur) < 1e-9 and rel(v, vr) < 1e-9
+    assert maxrel(u, orc.u()) < 1e-8 and maxrel(v, orc.v()) < 1e-8
+    assert maxrel(u, ur) < 1e-9 and maxrel(v, vr) < 1e-9
 
 
 # (model, workload, overrides, steps, tolerance on u, tolerance on v).  Measured errors: the
@@ -298,7 +298,7 @@ def test_steps_mixed_f32(model, name, over, n, tol_u, tol_v):
     ctx.step(p.dt, n)
     t, u, v = ctx.get_state()
     orc.run(p.dt, n)
-    eu, ev = rel(u, orc.u()), rel(v, orc.v())
+    eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
     say(f"  rel err u {eu:.2e} v {ev:.2e}")
     assert eu < tol_u and ev < tol_v
 
@@ -322,4 +322,4 @@ def test_autotune_keeps_state_and_parity(name, over):
     ctx.step(p.dt, 3)
     t, u, v = ctx.get_state()
     orc.run(p.dt, 5)
-    assert rel(u, orc.u()) < 1e-8 and rel(v, orc.v()) < 1e-8
+    assert maxrel(u, orc.u()) < 1e-8 and maxrel(v, orc.v()) < 1e-8
