@@ -351,6 +351,26 @@ static bool lattice_dims(const Inst& I, int lat[3]) {
   return true;
 }
 
+// Tolerance of the congruence test: 1e-13, or 32 eps R / h when larger, R the largest node
+// coordinate magnitude and h the mean element size (cube root of the bounding-box volume per
+// element): the rounding of the coordinates themselves leaves relative differences of about
+// eps R / h between the edges of otherwise identical elements.
+static double congruence_tol(const Inst& I) {
+  if (I.n_nodes < 1 || I.n_elems < 1) return 1e-13;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, R = 0.0;
+  for (int64_t n = 0; n < I.n_nodes; ++n)
+    for (int d = 0; d < 3; ++d) {
+      const double x = I.xyz[(size_t)n * 3 + d];
+      lo[d] = std::min(lo[d], x);
+      hi[d] = std::max(hi[d], x);
+      R = std::max(R, std::fabs(x));
+    }
+  const double vol = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+  if (!(vol > 0.0)) return 1e-13;
+  const double h = std::cbrt(vol / (double)I.n_elems);
+  return std::max(1e-13, 32.0 * 2.220446049250313e-16 * R / h);
+}
+
 static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   hipStream_t st = c->stream;
   build_incidence(I);
@@ -376,7 +396,7 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   int* flags = dptr<int>(c, I.o_flags);
   launch_geometry(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_conn), (int)I.n_elems, dptr<double>(c, I.o_geo),
                   dptr<float>(c, I.o_geo32), dptr<double>(c, I.o_vdet), flags + 0, st);
-  launch_congruence(dptr<double>(c, I.o_geo), (int)I.n_elems, flags + 1, st);
+  launch_congruence(dptr<double>(c, I.o_geo), (int)I.n_elems, congruence_tol(I), flags + 1, st);
   EP_HIP(c, hipGetLastError());
   launch_mass((int)I.n_nodes, (int)I.n_elems, dptr<int>(c, I.o_incp), dptr<int>(c, I.o_inc),
               dptr<double>(c, I.o_vdet), I.rho, dptr<unsigned char>(c, I.o_clamp), dptr<double>(c, I.o_mih),
@@ -1314,7 +1334,8 @@ ep_status ep_batch_get_state(ep_ctx* c, int32_t id, double* t, double* u, double
   return EP_OK;
 }
 
-ep_status ep_batch_get_stats(ep_ctx* c, int32_t id, int64_t* matvecs, int* last_m, int* last_k, double* last_eps) {
+ep_status ep_batch_get_stats(ep_ctx* c, int32_t id, int64_t* matvecs, int* last_m, int* last_k, double* last_eps,
+                             int64_t* matvecs_pred, int* last_m_pred, int* last_k_pred) {
   ep_status s = need_batch(c, id);
   if (s != EP_OK) return s;
   EP_HIP(c, hipStreamSynchronize(c->stream));
@@ -1324,6 +1345,9 @@ ep_status ep_batch_get_stats(ep_ctx* c, int32_t id, int64_t* matvecs, int* last_
   if (last_m) *last_m = h.ks[0].last_m;
   if (last_k) *last_k = h.ks[0].last_k;
   if (last_eps) *last_eps = h.ks[0].last_eps;
+  if (matvecs_pred) *matvecs_pred = h.ks[1].matvecs;
+  if (last_m_pred) *last_m_pred = h.ks[1].last_m;
+  if (last_k_pred) *last_k_pred = h.ks[1].last_k;
   return EP_OK;
 }
 

@@ -80,10 +80,12 @@ __global__ void k_geometry(const double* __restrict__ xyz, const int* __restrict
 }
 
 // flag elements whose Gauss-point geometry differs from element 0's
-// An element is congruent to element 0 when every J^{-1} entry agrees to 1e-13 of the
+// An element is congruent to element 0 when every J^{-1} entry agrees to `tol` of the
 // largest J^{-1} entry of that quadrature point (entries that vanish in exact arithmetic
-// carry rounding noise) and det J agrees to 1e-13 relative.
-__global__ void k_congruence(const double* __restrict__ geo, int n_e, int* __restrict__ mismatch) {
+// carry rounding noise) and det J agrees to `tol` relative.  The host sets tol from the
+// representation noise of the node coordinates: an edge of length h between nodes at
+// distance R from the origin carries a relative error of about eps R / h.
+__global__ void k_congruence(const double* __restrict__ geo, int n_e, double tol, int* __restrict__ mismatch) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)n_e * 80) return;
   const int r = (int)(idx % 80);
@@ -94,7 +96,7 @@ __global__ void k_congruence(const double* __restrict__ geo, int n_e, int* __res
   } else {
     scale = fabs(geo[r]);
   }
-  if (fabs(geo[idx] - geo[r]) > 1e-13 * scale + 1e-300) atomicOr(mismatch, 1);
+  if (fabs(geo[idx] - geo[r]) > tol * scale + 1e-300) atomicOr(mismatch, 1);
 }
 
 // lumped mass by the vertex rule, M_A = rho * sum of vertex det J of the elements around A
@@ -454,8 +456,8 @@ void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, f
                      hipStream_t st) {
   if (n_e > 0) k_geometry<<<nblk(n_e, 128), 128, 0, st>>>(xyz, conn, n_e, geo, geo32, vdet, bad);
 }
-void launch_congruence(const double* geo, int n_e, int* mismatch, hipStream_t st) {
-  if (n_e > 0) k_congruence<<<nblk((long long)n_e * 80, 256), 256, 0, st>>>(geo, n_e, mismatch);
+void launch_congruence(const double* geo, int n_e, double tol, int* mismatch, hipStream_t st) {
+  if (n_e > 0) k_congruence<<<nblk((long long)n_e * 80, 256), 256, 0, st>>>(geo, n_e, tol, mismatch);
 }
 void launch_mass(int n_nodes, int n_e, const int* inc_ptr, const int* inc, const double* vdet, double rho,
                  const unsigned char* clamp, double* mih, double* mh, hipStream_t st) {

@@ -15,7 +15,7 @@ hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
 
 void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,
                      hipStream_t st);
-void launch_congruence(const double* geo, int n_e, int* mismatch, hipStream_t st);
+void launch_congruence(const double* geo, int n_e, double tol, int* mismatch, hipStream_t st);
 void launch_mass(int n_nodes, int n_e, const int* inc_ptr, const int* inc, const double* vdet, double rho,
                  const unsigned char* clamp, double* mih, double* mh, hipStream_t st);
 void launch_faces(const double* xyz, const int* faces, int n_f, const double* t0, double* ff, int n_nodes,
