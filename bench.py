@@ -1,17 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the exponential propagator's hot path on one MI355X.
 
-Headline workload: linear steel cantilever 80x8x8 hex8 (6,561 nodes, 19,440 free DOFs),
-E = 200 GPa, nu = 0.3, rho = 7800, x = 0 clamped, tip traction 1e5 Pa (-z), initial
-velocity N(0, (1e-3 m/s)^2) per free DOF (seed 0), dt = 1e-4 s, Krylov tol 1e-10, FP64.
-As in the paper's production runs (Sec. 6.2) the subspace size (and substep count) is
-calibrated on the warm-up steps by the adaptive error estimate, then held fixed.
+Headline workload (the metric's own configuration): 256 independent compressible
+Neo-Hookean rubber blocks of uneven size (nx ~ U{20..60}, ny = nz ~ U{4..8}, 1 cm cells;
+mu ~ U[0.2, 1] MPa, lambda = 5 mu, rho 1100; x = 0 clamped; constant tip traction
+~ U[1e3, 1e4] Pa in -z; from rest; seed 5), advanced together by one persistent launch per
+time step (captured graph), dt = 2.5e-5 s, Krylov tol 1e-10, adaptive subspace per instance.
+The mixed form (FP32 operator, FP64 Krylov / exponential / state) is timed, and the plain
+FP64 form on the same instances, the same dt and the same steps beside it; both report the
+relative energy error (from rest under a constant load, E_0 = 0:
+|KE + SE - W| / (KE + SE)), which must be <= 1e-6 for the comparison to hold.
 
-value = DOF-matvecs/s = free DOFs x Hbar applications / s (time-steps/s beside it).
-Extra fields (same JSON line): the mixed-precision operator on the same workload, the
-nonlinear Neo-Hookean / Yeoh workloads and the 256-instance batch, each with FP64 and mixed
-throughput and the relative energy error, plus the roofline of the dominant kernel and the
-oracle timed on the host cores.
+value = DOF-matvecs/s of the mixed batch = sum over instances of free DOFs x Hbar
+applications / s; time-steps/s (batch steps) and instance-steps/s beside it.
+roofline: the batch kernel k_batch (one launch per step), algorithmic bytes per launch from
+the per-instance operator and Gram-Schmidt traffic, over its average launch duration.
+cpu_baseline: the FP64 oracle on 16 instances spanning the sizes, in parallel worker
+processes (one thread each), for a bounded time; extrapolated to the batch as a rate.
+Extras (labelled): the single-instance workloads (steel cantilever 80x8x8, Neo-Hookean
+cantilever 160x16x16, Yeoh 64^3 block) on short step subsets, stand-alone operator applies
+(incl. a 192^3 cube beyond the Infinity Cache) and the BF16 tangent formation.
 """
 from __future__ import annotations
 
@@ -33,9 +41,13 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--instances", type=int, default=256, help="batch size of the headline workload")
+    ap.add_argument("--batch-dt", type=float, default=2.5e-5)
+    ap.add_argument("--batch-m-max", type=int, default=32)
+    ap.add_argument("--headline-only", action="store_true", help="only the batch (profiling)")
+    ap.add_argument("--config", default="c2", help="single-instance workload of the extras")
     ap.add_argument("--dt", type=float, default=1e-4)
     ap.add_argument("--m-max", type=int, default=64)
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed_f32", "mixed_bf16"])
@@ -72,40 +84,32 @@ def log(args, *a):
 
 
 def algorithmic_bytes(prob, m, k, s_x=8, projections=1):
-    """Algorithmic HBM bytes of one projection launch (k substeps of m Arnoldi steps).
-
-    Operator apply (per application): read x (u- and v-part, 2*3n), write y (2*3n),
-    connectivity (32 B per element), M^{-1/2} (3n) and the load vector (3n).
-    Arnoldi-MGS (per projection of size m): step j reads v_1..v_j and writes v_{j+1}:
-    L*m(m+1)/2 reads and L*(m+1) writes; the combination reads m vectors and writes one,
-    plus the initial read of w.  L = 2*3n + 1 doubles.
-    """
+    """Algorithmic HBM bytes of one single-instance projection launch (k substeps of m
+    Arnoldi steps), as the batch's per instance: operator apply = read x, write y (2 * 3n
+    values of s_x bytes), connectivity (32 B per element), M^{-1/2} (3n values); Arnoldi-MGS
+    on L = 2 N_free + 1 FP64 entries reads L m(m+1)/2 and writes L (m+1) doubles, the
+    combination reads m vectors."""
     n3 = 3 * prob.n_nodes
-    L = 2 * n3 + 1
-    per_mv = (4 * n3 + 2 * n3) * s_x + 32 * prob.n_elems
-    per_proj = m * per_mv + 8 * L * (m * (m + 1) // 2 + (m + 1) + m + 2)
+    L = 2 * prob.n_free + 1
+    per_mv = (2 * n3 + n3) * s_x + 32 * prob.n_elems
+    per_proj = m * per_mv + 8 * L * (m * (m + 1) // 2 + (m + 1) + m)
     return projections * k * per_proj
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_expv_c2_linear_f64_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_batch_c5_rubber256_mixed_traffic.json")
 
 
-def kernel_sources_sha256():
-    from paper_2405_05213_amd.profsum import projection_kernel_sha256
-    return projection_kernel_sha256()
-
-
-def measured_traffic(config_name, precision, m, k, workgroups):
-    """HBM bytes per launch of the headline kernel from the committed rocprofv3 counter runs
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the batch kernel from the committed rocprofv3 counter runs
     (FETCH_SIZE / WRITE_SIZE scaled by a copy kernel of known size), or None when the kernel
-    sources or the launch configuration differ from the profiled ones."""
+    sources or the workload differ from the profiled ones."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
+    from paper_2405_05213_amd.profsum import batch_kernel_sha256
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
-    same = (rec.get("kernel_sources_sha256") == kernel_sources_sha256()
-            and rec.get("config") == config_name and rec.get("precision") == precision
-            and rec.get("m") == m and rec.get("k") == k and rec.get("workgroups") == workgroups)
+    same = (rec.get("kernel_sources_sha256") == batch_kernel_sha256() and rec.get("workload") == workload
+            and rec.get("precision") == precision)
     return float(rec["traffic_bytes_per_launch"]) if same else None
 
 
@@ -149,7 +153,7 @@ def run_single(prob, precision, steps, warmup, m_max, workgroups, adaptive, stre
     if adaptive:
         ctx = cal
     else:
-        del cal
+        cal.close()
         ctx = solver_from_problem(prob, m_max=m_max, m_fixed=max(m_cal, m_pred), k_fixed=k_cal,
                                   precision=precision, workgroups=tuned_G, stream=stream.cuda_stream,
                                   ortho=args.ortho)
@@ -225,7 +229,8 @@ def run_matvec(prob, u_lin, reps, stream, torch, args):
     alg = (2 * n3 + (n3 if u is not None else 0)) * 8 + (32 * prob.n_elems if reads_conn else 0)
     achieved = alg / (us * 1e-6) / 1e9
     log(args, f"  matvec {prob.name} {prob.model} {prob.grid}: {us:.2f} us/apply, {achieved:.0f} GB/s ({path})")
-    del graph, ctx
+    del graph
+    ctx.close()
     return {"us_per_apply": us, "dofs": n3, "elements": prob.n_elems, "path": path, "graph_replay_matches": ok,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "alg_bytes_per_apply": alg}}
@@ -292,33 +297,125 @@ def run_tangents(prob, u_lin, reps, stream, torch, args):
                            "frac_hbm": gbs / HBM_PEAK_GBS, "flops_per_formation": flops,
                            "alg_bytes_per_formation": alg_bytes},
     })
-    del ctx
+    ctx.close()
     return out
 
 
-def run_batch(probs, precision, steps, m_max, stream, torch, args):
+def batch_algorithmic_bytes(probs, per_inst, s_x):
+    """Algorithmic HBM bytes of one batch launch (one time step of every instance).
+
+    Per operator apply of an instance (n = nodes, e = elements): read x, write y (2 * 3n
+    values of s_x bytes), the connectivity (32 B per element), M^{-1/2} (3n values) and the
+    nodal linearisation displacement (3n values; two sets in the predictor).  Per projection of
+    size m on L = 2 N_free + 1 FP64 entries: Arnoldi-MGS reads L m(m+1)/2 and writes L (m+1)
+    doubles, the combination reads m vectors.  per_inst: (m_corr, k_corr, m_pred, k_pred)."""
+    tot = 0
+    for p, (mc, kc, mp, kp) in zip(probs, per_inst):
+        n3 = 3 * p.n_nodes
+        L = 2 * p.n_free + 1
+        mv = lambda sets: (2 * n3 + n3 + sets * n3) * s_x + 32 * p.n_elems
+        mgs = lambda m: 8 * L * (m * (m + 1) // 2 + (m + 1) + m)
+        tot += kc * (mc * mv(1) + mgs(mc)) + kp * (mp * mv(2) + mgs(mp))
+    return tot
+
+
+def run_batch(probs, precision, steps, warmup, m_max, stream, torch, args):
     from paper_2405_05213_amd import batch_from_problems
     b = batch_from_problems(probs, m_max=m_max, precision=precision, stream=stream.cuda_stream)
     dt = probs[0].dt
-    b.step(dt, 2)
+    b.step(dt, max(1, warmup))
     b.sync()
-    mv0 = sum(b.stats(i)["matvecs"] for i in range(len(probs)))
+    st0 = [b.stats(i) for i in range(len(probs))]
     ms, wall = timed_steps(b, dt, steps, stream, torch)
     b.sync()
-    mv1 = sum(b.stats(i)["matvecs"] for i in range(len(probs)))
+    st1 = [b.stats(i) for i in range(len(probs))]
     gpu_s = float(ms.sum()) / 1e3
+    n_free = np.array([p.n_free for p in probs])
+    mv = np.array([a["matvecs"] - z["matvecs"] for a, z in zip(st1, st0)])
+    mvp = np.array([a["matvecs_pred"] - z["matvecs_pred"] for a, z in zip(st1, st0)])
+    # per-instance projection sizes over the timed steps (matvecs per projection)
+    per_inst = []
+    for i in range(len(probs)):
+        kc, kp = max(1, st1[i]["k"]), max(1, st1[i]["k_pred"])
+        mc = (mv[i] - mvp[i]) / (steps * kc)
+        mp = mvp[i] / (steps * kp)
+        per_inst.append((int(round(mc)), kc, int(round(mp)), kp))
     # constant loads from rest: E_0 = 0, so the energy error is |KE + SE - W| / (KE + SE)
-    errs = []
-    for i in range(0, len(probs), max(1, len(probs) // 16)):
-        errs.append(energy_err((0.0, 0.0, 0.0), b.energy(i)))
-    n_free = [p.n_free for p in probs]
-    log(args, f"  batch {len(probs)} {precision}: {np.mean(ms):.3f} ms/step")
-    return {
-        "ms_per_step": float(np.mean(ms)), "instance_steps_per_s": len(probs) * steps / gpu_s,
+    errs = np.array([energy_err((0.0, 0.0, 0.0), b.energy(i)) for i in range(len(probs))])
+    alg = batch_algorithmic_bytes(probs, per_inst, 8 if precision == "f64" else 4)
+    launch_ms = float(np.mean(ms))
+    log(args, f"  batch {len(probs)} {precision}: {launch_ms:.3f} ms/step, energy err max {errs.max():.2e}")
+    out = {
+        "ms_per_step": launch_ms, "instance_steps_per_s": len(probs) * steps / gpu_s,
         "time_steps_per_s": steps / gpu_s,
-        "dof_matvecs_per_s": float(np.mean(n_free)) * (mv1 - mv0) / gpu_s,
-        "energy_rel_err_max": float(max(errs)), "instances": len(probs), "total_free_dofs": int(sum(n_free)),
+        "dof_matvecs_per_s": float((n_free * mv).sum()) / gpu_s,
+        "energy_rel_err_max": float(errs.max()), "energy_rel_err_median": float(np.median(errs)),
+        "instances": len(probs), "total_free_dofs": int(n_free.sum()),
+        "matvecs_per_step": float(mv.sum()) / steps,
+        "m_corr_range": [min(q[0] for q in per_inst), max(q[0] for q in per_inst)],
+        "m_pred_range": [min(q[2] for q in per_inst), max(q[2] for q in per_inst)],
+        "alg_bytes_per_launch": alg, "wall_s": wall,
     }
+    b.close()
+    return out
+
+
+def _cpu_worker(args):
+    """Oracle steps of one instance for about `seconds` (one thread); returns
+    (free DOFs x H applications, steps, seconds)."""
+    prob, seconds = args
+    from threadpoolctl import threadpool_limits
+    from oracle.stepper import Propagator
+    with threadpool_limits(1):
+        orc = Propagator(prob, m_max=32)
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds or n == 0:
+            orc.step(prob.dt)
+            n += 1
+        el = time.perf_counter() - t0
+    return prob.n_free * orc.matvecs, n, el
+
+
+def cpu_baseline_batch(probs, seconds, args):
+    """The FP64 oracle (as it stands) on 16 instances spanning the batch's sizes, one worker
+    process per instance (one thread each), for about `seconds` each.  Run before the GPU is
+    touched (the workers are forked)."""
+    import multiprocessing as mp
+    order = np.argsort([p.n_free for p in probs])
+    pick = [probs[i] for i in order[np.linspace(0, len(probs) - 1, min(16, len(probs))).round().astype(int)]]
+    procs = max(1, min(len(pick), os.cpu_count() or 1, 16))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_cpu_worker, [(p, seconds) for p in pick])
+    wall = time.perf_counter() - t0
+    dofmv = sum(r[0] for r in res)
+    thread_s = sum(r[2] for r in res)
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    log(args, f"  cpu baseline: {dofmv / wall:.3e} DOF-matvecs/s on {procs} processes ({cpu})")
+    return {"value": dofmv / wall, "unit": "DOF-matvecs/s", "cores": procs, "kind": "oracle",
+            "per_thread_value": dofmv / thread_s,
+            "instance_steps_per_s": sum(r[1] for r in res) / wall,
+            "host_cpu": cpu, "host_logical_cpus": os.cpu_count(),
+            "sample": (f"{len(pick)} of the {len(probs)} instances (evenly spaced in size, {pick[0].n_free}.."
+                       f"{pick[-1].n_free} free DOFs), about {seconds:g} s of oracle steps each (dt, tol and "
+                       f"m_max as the GPU run), NumPy FP64, one process and one thread per instance, "
+                       f"{procs} processes in parallel; extrapolated to the whole batch as a rate")}
+
+
+def batch_workload(probs, dt, m_max):
+    nx = [p.grid[0] for p in probs]
+    nyz = [p.grid[1] for p in probs]
+    return (f"c5: {len(probs)} compressible Neo-Hookean rubber blocks, hex8 nx {min(nx)}..{max(nx)} x "
+            f"ny=nz {min(nyz)}..{max(nyz)}, {sum(p.n_free for p in probs)} free DOFs in all, dt={dt:g} s, "
+            f"tol=1e-10, m_max={m_max} adaptive per instance, one launch per step")
 
 
 def main():
@@ -327,14 +424,18 @@ def main():
         print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding over several "
                                    "GPUs is not built)"}))
         sys.exit(2)
-    import torch
     from workloads import config, batch_instances
+    probs = batch_instances(args.instances, seed=5, dt=args.batch_dt)
+    # the oracle on the host cores first: its worker processes are forked before the GPU is touched
+    cpu = None
+    if not (args.no_cpu or args.matvec_only or args.tangents_only):
+        cpu = cpu_baseline_batch(probs, args.cpu_seconds, args)
+    import torch
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     stream = torch.cuda.current_stream()
-    prob = config(args.config, dt=args.dt)
     if args.copy_probe:
         copy_probe(torch)
     if args.matvec_only:
@@ -346,112 +447,126 @@ def main():
         print(json.dumps({"tangents_cube64_yeoh_bf16": run_tangents(cube, u_aff, 20, stream, torch, args)}))
         return
 
-    head = run_single(prob, args.precision, args.steps, args.warmup, args.m_max, args.workgroups,
-                      args.adaptive, stream, torch, args)
-    m_used, k_used = head["m"], head["k"]
-    alg = algorithmic_bytes(prob, m_used, k_used)
-    launch_s = head["ms_per_step"] / 1e3
-    achieved = alg / launch_s / 1e9
+    mixed = run_batch(probs, "mixed_f32", args.steps, args.warmup, args.batch_m_max, stream, torch, args)
+    f64 = run_batch(probs, "f64", args.steps, args.warmup, args.batch_m_max, stream, torch, args)
+    workload = batch_workload(probs, args.batch_dt, args.batch_m_max)
+    launch_s = mixed["ms_per_step"] / 1e3
+    achieved = mixed["alg_bytes_per_launch"] / launch_s / 1e9
+    gate = max(mixed["energy_rel_err_max"], f64["energy_rel_err_max"]) <= 1e-6
     result = {
-        "metric": "DOF-matvecs/s (+ time-steps/s) at fixed energy error",
-        "value": head["dof_matvecs_per_s"],
+        "metric": "DOF-matvecs/s + time-steps/s at fixed energy error, mixed/batched vs FP64",
+        "value": mixed["dof_matvecs_per_s"],
         "unit": "DOF-matvecs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f64": "f64", "mixed_f32": "f64 (Krylov) / f32 (operator)",
-                  "mixed_bf16": "f64 (Krylov) / bf16 tangents, f32 apply"}[args.precision],
+        "dtype": "f32 operator, f64 Krylov/expm/state",
         "data": "synthetic",
-        "config": {
-            "workload": f"{args.config}: linear steel cantilever {prob.grid[0]}x{prob.grid[1]}x{prob.grid[2]} hex8, "
-                        f"{prob.n_free} free DOFs, dt={prob.dt:g} s, tol={prob.tol:g}",
-            "dt": prob.dt, "m": m_used, "substeps": k_used,
-            "m_mode": "adaptive" if args.adaptive else "calibrated then fixed",
-            "precision": args.precision, "free_dofs": prob.n_free, "workgroups": head["workgroups"],
-            "gram_schmidt": "compact-WY MGS" if head["ortho"] == 1 else "sequential MGS",
-        },
-        "time_steps_per_s": head["time_steps_per_s"],
-        "energy_rel_err": head["energy_rel_err"],
+        "config": {"workload": workload, "instances": len(probs), "dt": args.batch_dt, "tol": 1e-10,
+                   "m_max": args.batch_m_max, "precision": "mixed_f32",
+                   "total_free_dofs": mixed["total_free_dofs"]},
+        "time_steps_per_s": mixed["time_steps_per_s"],
+        "instance_steps_per_s": mixed["instance_steps_per_s"],
+        "energy_rel_err_max": mixed["energy_rel_err_max"],
+        "fp64_same_workload": {k: f64[k] for k in ("dof_matvecs_per_s", "time_steps_per_s", "instance_steps_per_s",
+                                                   "ms_per_step", "energy_rel_err_max", "energy_rel_err_median",
+                                                   "matvecs_per_step", "m_corr_range", "m_pred_range")},
+        "mixed_vs_fp64": {"time_steps_per_s": mixed["time_steps_per_s"] / f64["time_steps_per_s"],
+                          "dof_matvecs_per_s": mixed["dof_matvecs_per_s"] / f64["dof_matvecs_per_s"],
+                          "energy_gate_1e-6_met_by_both": gate},
+        "headline_detail": {k: mixed[k] for k in ("energy_rel_err_median", "matvecs_per_step", "m_corr_range",
+                                                  "m_pred_range")},
         "roofline": {
-            "kernel": "k_expv (persistent Arnoldi-MGS projection incl. operator applies), one launch per step",
+            "kernel": "k_batch<float, 1> (one workgroup per instance: operator applies, Arnoldi-MGS, exponential, "
+                      "predictor and corrector of one time step), one launch per step",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.config, args.precision, m_used, k_used, head["workgroups"]),
-            "alg_bytes_per_launch": alg, "avg_launch_ms": launch_s * 1e3,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, "mixed_f32"),
+            "alg_bytes_per_launch": mixed["alg_bytes_per_launch"], "avg_launch_ms": launch_s * 1e3,
         },
     }
-    _, u_head, v_head = head["ctx"].get_state()
-    del head["ctx"]
-
-    if not args.no_extra:
-        extra = {}
-        mixed = run_single(prob, "mixed_f32", args.steps, args.warmup, args.m_max, args.workgroups, args.adaptive,
-                           stream, torch, args)
-        extra["c2_mixed_f32"] = {k: v for k, v in mixed.items() if k not in ("ctx", "step_ms")}
-        # the same steps as the FP64 headline run: error of the final state against it
-        _, u_mix, v_mix = mixed["ctx"].get_state()
-        extra["c2_mixed_f32"]["state_rel_err_vs_f64"] = {
-            "u": float(np.linalg.norm(u_mix - u_head) / np.linalg.norm(u_head)),
-            "v": float(np.linalg.norm(v_mix - v_head) / np.linalg.norm(v_head))}
-        del mixed
-        # the c2 workload's time-step sweep (FP64): the subspace size and substeps the adaptive
-        # choice settles on, and the cost of one simulated second at each step size
-        sweep = {}
-        for dt in (1e-5, 1e-4, 1e-3):
-            r = run_single(config(args.config, dt=dt), "f64", 10, 3, args.m_max, args.workgroups, False,
-                           stream, torch, args)
-            sweep[f"{dt:g}"] = {"ms_per_step": r["ms_per_step"], "m": r["m"], "k": r["k"],
-                                "time_steps_per_s": r["time_steps_per_s"],
-                                "dof_matvecs_per_s": r["dof_matvecs_per_s"],
-                                "gpu_s_per_simulated_s": r["ms_per_step"] / 1e3 / dt}
-            del r
-        extra["c2_dt_sweep_f64"] = sweep
-        for name, dt, steps in (("c3", 1e-4, 20), ("c4", 1e-3, 8)):
-            p = config(name, dt=dt)
-            ref_state = None
-            for prec in ("f64", "mixed_f32", "mixed_bf16"):
-                r = run_single(p, prec, steps, 3, 64, 0, True, stream, torch, args)
-                e = {k: v for k, v in r.items() if k not in ("ctx", "step_ms", "energy_rel_err")}
-                e["free_dofs"] = p.n_free
-                # time-varying load: error of the final state (warm-up + timed steps, same
-                # steps in every precision) against the FP64 run, which matches the oracle to 1e-8
-                _, u, v = r["ctx"].get_state()
-                en = r["ctx"].energy()
-                if ref_state is None:
-                    ref_state = (u, v, en)
-                else:
-                    ur, vr, er = ref_state
-                    e["state_rel_err_vs_f64"] = {
-                        "u": float(np.linalg.norm(u - ur) / np.linalg.norm(ur)),
-                        "v": float(np.linalg.norm(v - vr) / np.linalg.norm(vr)),
-                        "energy": abs((en[0] + en[1] - en[2]) - (er[0] + er[1] - er[2])) / (er[0] + er[1])}
-                extra[f"{name}_{prec}"] = e
-                del r
-        extra.update(run_matvecs(config, stream, torch, args))
-        cube = config("c4")
-        u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
-        extra["tangents_cube64_yeoh_bf16"] = run_tangents(cube, u_aff, 20, stream, torch, args)
-        probs = batch_instances(256, seed=5, dt=2.5e-5)
-        for prec in ("f64", "mixed_f32"):
-            extra[f"c5_batch_{prec}"] = run_batch(probs, prec, 30, 32, stream, torch, args)
-        result["extra"] = extra
-
-    if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(prob, m_used, k_used, args)
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
+    if not (args.headline_only or args.no_extra):
+        result["extra"] = run_extras(config, stream, torch, args)
     print(json.dumps(result))
 
 
+def run_extras(config, stream, torch, args):
+    """Single-instance workloads on short step subsets (labelled), stand-alone applies and
+    the BF16 tangents."""
+    extra = {}
+    prob = config(args.config, dt=args.dt)
+    states = {}
+    for prec in ("f64", "mixed_f32"):
+        r = run_single(prob, prec, 30, args.warmup, args.m_max, args.workgroups, args.adaptive, stream, torch, args)
+        m_used, k_used = r["m"], r["k"]
+        alg = algorithmic_bytes(prob, m_used, k_used, s_x=8 if prec == "f64" else 4)
+        e = {k: v for k, v in r.items() if k not in ("ctx", "step_ms")}
+        e["subset"] = f"30 timed steps after {args.warmup} calibration steps (the workload runs 500)"
+        e["roofline_k_expv"] = {"achieved": alg / (r["ms_per_step"] / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": alg / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                "alg_bytes_per_launch": alg}
+        _, u, v = r["ctx"].get_state()
+        states[prec] = (u, v)
+        if prec != "f64":
+            u0, v0 = states["f64"]
+            e["state_rel_err_vs_f64"] = {"u": float(np.abs(u - u0).max() / np.abs(u0).max()),
+                                         "v": float(np.abs(v - v0).max() / np.abs(v0).max())}
+        r["ctx"].close()
+        extra[f"{args.config}_{prec}"] = e
+    # the c2 workload's time-step sweep (FP64): the subspace size and substeps the adaptive
+    # choice settles on, and the cost of one simulated second at each step size
+    sweep = {}
+    for dt in (1e-5, 1e-4, 1e-3):
+        r = run_single(config(args.config, dt=dt), "f64", 10, 3, args.m_max, args.workgroups, False,
+                       stream, torch, args)
+        sweep[f"{dt:g}"] = {"ms_per_step": r["ms_per_step"], "m": r["m"], "k": r["k"],
+                            "time_steps_per_s": r["time_steps_per_s"],
+                            "dof_matvecs_per_s": r["dof_matvecs_per_s"],
+                            "gpu_s_per_simulated_s": r["ms_per_step"] / 1e3 / dt}
+        r["ctx"].close()
+    extra["c2_dt_sweep_f64"] = sweep
+    for name, dt, steps in (("c3", 1e-4, 20), ("c4", 1e-3, 8)):
+        p = config(name, dt=dt)
+        ref_state = None
+        for prec in ("f64", "mixed_f32", "mixed_bf16"):
+            r = run_single(p, prec, steps, 3, 64, 0, True, stream, torch, args)
+            e = {k: v for k, v in r.items() if k not in ("ctx", "step_ms", "energy_rel_err")}
+            e["free_dofs"] = p.n_free
+            e["subset"] = f"{steps} timed steps after 3 warm-up steps (the workload runs {p.n_steps})"
+            # time-varying load: error of the final state (warm-up + timed steps, same
+            # steps in every precision) against the FP64 run, which matches the oracle to 1e-8
+            _, u, v = r["ctx"].get_state()
+            en = r["ctx"].energy()
+            if ref_state is None:
+                ref_state = (u, v, en)
+            else:
+                ur, vr, er = ref_state
+                e["state_rel_err_vs_f64"] = {
+                    "u": float(np.abs(u - ur).max() / np.abs(ur).max()),
+                    "v": float(np.abs(v - vr).max() / np.abs(vr).max()),
+                    "energy": abs((en[0] + en[1] - en[2]) - (er[0] + er[1] - er[2])) / (er[0] + er[1])}
+            r["ctx"].close()
+            extra[f"{name}_{prec}"] = e
+    extra.update(run_matvecs(config, stream, torch, args))
+    cube = config("c4")
+    u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
+    extra["tangents_cube64_yeoh_bf16"] = run_tangents(cube, u_aff, 20, stream, torch, args)
+    return extra
+
+
 def run_matvecs(config, stream, torch, args):
-    """The stand-alone FP64 applies: linear 64^3 and 128^3 cubes (lattice path) and the Yeoh
+    """The stand-alone FP64 applies: linear 64^3, 128^3 and 192^3 cubes (lattice path) and the Yeoh
     secant apply on the 64^3 block at an affine deformation."""
     import dataclasses
     out = {}
     cube = config("c4")
-    for nx in (64, 128):
+    # 192^3: x and y alone are 0.34 GB, beyond the 256 MB Infinity Cache (the roofline probe)
+    for nx in (64, 128, 192):
         q = cube if nx == 64 else config("c4", nx=nx, ny=nx, nz=nx)
         q = dataclasses.replace(q, model="linear", params=(200e9, 0.3), rho=7800.0)
         out[f"matvec_cube{nx}_linear_f64"] = run_matvec(q, None, 50, stream, torch, args)
@@ -459,23 +574,6 @@ def run_matvecs(config, stream, torch, args):
     u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
     out["matvec_cube64_yeoh_f64"] = run_matvec(cube, u_aff, 20, stream, torch, args)
     return out
-
-
-def cpu_baseline(prob, m, k, args):
-    from threadpoolctl import threadpool_limits
-    from oracle.stepper import Propagator
-    with threadpool_limits(1):
-        orc = Propagator(prob, m_max=max(m, 1), m_fixed=m, k_fixed=k)
-        n = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < args.cpu_seconds or n == 0:
-            orc.step(prob.dt)
-            n += 1
-        dt = time.perf_counter() - t0
-    return {"value": prob.n_free * orc.matvecs / dt, "unit": "DOF-matvecs/s", "cores": 1, "kind": "oracle",
-            "time_steps_per_s": n / dt,
-            "sample": f"{n} steps of the same workload (m={m}, k={k} fixed) by the NumPy FP64 oracle, 1 thread, "
-                      f"{platform.processor() or platform.machine()}"}
 
 
 if __name__ == "__main__":

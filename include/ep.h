@@ -303,9 +303,13 @@ ep_status ep_batch_step(ep_ctx* ctx, double dt, int64_t n_steps);
 /* As ep_get_state, for one instance (synchronising; returns that instance's failure only). */
 ep_status ep_batch_get_state(ep_ctx* ctx, int32_t instance_id, double* t, double* u_host,
                              double* v_host);
-/* Per-instance statistics of the last step: corrector m and substeps. */
+/* Per-instance statistics (synchronising): operator applies so far (both kinds), the last
+ * corrector (or linear) projection's m, substeps and error estimate, and - for the
+ * predictor projections of a nonlinear instance - their applies so far, last m and
+ * substeps (0 for a linear instance).  Any output may be NULL. */
 ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs, int* last_m,
-                             int* last_k, double* last_eps);
+                             int* last_k, double* last_eps, int64_t* matvecs_pred, int* last_m_pred,
+                             int* last_k_pred);
 /* Per-instance energies, as ep_get_energy. */
 ep_status ep_batch_get_energy(ep_ctx* ctx, int32_t instance_id, double* kinetic, double* strain,
                               double* ext_work);

@@ -71,7 +71,8 @@ _SIGS = {
     "ep_batch_set_state": [_vp, _i32, _dbl, _vp, _vp],
     "ep_batch_step": [_vp, _dbl, _i64],
     "ep_batch_get_state": [_vp, _i32, _P(_dbl), _vp, _vp],
-    "ep_batch_get_stats": [_vp, _i32, _P(_i64), _P(C.c_int), _P(C.c_int), _P(_dbl)],
+    "ep_batch_get_stats": [_vp, _i32, _P(_i64), _P(C.c_int), _P(C.c_int), _P(_dbl), _P(_i64), _P(C.c_int),
+                           _P(C.c_int)],
     "ep_batch_get_energy": [_vp, _i32, _P(_dbl), _P(_dbl), _P(_dbl)],
 }
 EXPORTED = sorted(_SIGS)
@@ -342,8 +343,11 @@ class Batch(Context):
 
     def stats(self, iid):
         mv, m, k, e = C.c_int64(), C.c_int(), C.c_int(), C.c_double()
-        self._call("ep_batch_get_stats", int(iid), C.byref(mv), C.byref(m), C.byref(k), C.byref(e))
-        return {"matvecs": mv.value, "m": m.value, "k": k.value, "eps": e.value}
+        mvp, mp, kp = C.c_int64(), C.c_int(), C.c_int()
+        self._call("ep_batch_get_stats", int(iid), C.byref(mv), C.byref(m), C.byref(k), C.byref(e), C.byref(mvp),
+                   C.byref(mp), C.byref(kp))
+        return {"matvecs": mv.value, "m": m.value, "k": k.value, "eps": e.value, "matvecs_pred": mvp.value,
+                "m_pred": mp.value, "k_pred": kp.value}
 
     def energy(self, iid):
         a, b, c = C.c_double(), C.c_double(), C.c_double()

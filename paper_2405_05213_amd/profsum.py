@@ -53,15 +53,27 @@ PROJECTION_KERNEL_SOURCES = ("ep_common.hpp", "ep_device.hpp", "ep_expm.hpp", "e
                              "ep_expv.hpp")
 
 
-def projection_kernel_sha256() -> str:
+# ... and those of the batch kernel (one workgroup per instance)
+BATCH_KERNEL_SOURCES = PROJECTION_KERNEL_SOURCES + ("ep_batch.hip",)
+
+
+def sources_sha256(files) -> str:
     import hashlib
     import os
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-    for f in PROJECTION_KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def projection_kernel_sha256() -> str:
+    return sources_sha256(PROJECTION_KERNEL_SOURCES)
+
+
+def batch_kernel_sha256() -> str:
+    return sources_sha256(BATCH_KERNEL_SOURCES)
 
 
 def _per_dispatch(db: str, counter: str, kernel_like: str):
@@ -85,13 +97,14 @@ def traffic(fetch_db: str, write_db: str, kernel: str, last: int, bench_json: st
     with open(bench_json) as fh:
         b = json.loads(fh.read().strip().splitlines()[-1])
     c = b["config"]
+    batch = "k_batch" in kernel
     return {"kernel": kernel, "workload": c["workload"],
             "dispatches": f"the {last} timed launches (last {last} dispatches of the kernel in each run)",
             "fetch_kib_per_launch": fetch, "write_kib_per_launch": write, "copy_probe_kib": copy_kib,
             "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": fs, "write_scale": ws,
             "traffic_bytes_per_launch": (fs * fetch + ws * write) * 1024.0,
-            "kernel_sources_sha256": projection_kernel_sha256(), "config": c["workload"].split(":")[0],
-            "precision": c["precision"], "m": c["m"], "k": c["substeps"], "workgroups": c["workgroups"]}
+            "kernel_sources_sha256": batch_kernel_sha256() if batch else projection_kernel_sha256(),
+            "precision": c["precision"]}
 
 
 def main():

@@ -1,5 +1,5 @@
 """Host-side logic of bench.py (no GPU): the one-GPU refusal, the rules under which the
-committed counter record supplies `roofline.traffic`, and the algorithmic byte count."""
+committed counter record supplies `roofline.traffic`, and the algorithmic byte counts."""
 import json
 import os
 import subprocess
@@ -10,7 +10,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 import bench  # noqa: E402
-from workloads import config  # noqa: E402
+from paper_2405_05213_amd.profsum import batch_kernel_sha256  # noqa: E402
+from workloads import batch_instances, config  # noqa: E402
 
 
 def test_more_than_one_gpu_is_refused():
@@ -21,45 +22,60 @@ def test_more_than_one_gpu_is_refused():
 
 
 def _record(tmp_path, **over):
-    rec = {"kernel_sources_sha256": bench.kernel_sources_sha256(), "config": "c2", "precision": "f64",
-           "m": 48, "k": 4, "workgroups": 80, "traffic_bytes_per_launch": 1.25e9}
+    rec = {"kernel_sources_sha256": batch_kernel_sha256(), "workload": "W", "precision": "mixed_f32",
+           "traffic_bytes_per_launch": 1.25e9}
     rec.update(over)
     p = tmp_path / "traffic.json"
     p.write_text(json.dumps(rec))
     return str(p)
 
 
-def test_traffic_only_for_the_profiled_kernel_and_launch(tmp_path, monkeypatch):
+def test_traffic_only_for_the_profiled_kernel_and_workload(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "TRAFFIC_FILE", _record(tmp_path))
-    assert bench.measured_traffic("c2", "f64", 48, 4, 80) == 1.25e9
-    for args in (("c3", "f64", 48, 4, 80), ("c2", "mixed_f32", 48, 4, 80), ("c2", "f64", 40, 4, 80),
-                 ("c2", "f64", 48, 2, 80), ("c2", "f64", 48, 4, 96)):
-        assert bench.measured_traffic(*args) is None
+    assert bench.measured_traffic("W", "mixed_f32") == 1.25e9
+    assert bench.measured_traffic("W2", "mixed_f32") is None
+    assert bench.measured_traffic("W", "f64") is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", _record(tmp_path, kernel_sources_sha256="0" * 64))
-    assert bench.measured_traffic("c2", "f64", 48, 4, 80) is None      # kernel changed since
+    assert bench.measured_traffic("W", "mixed_f32") is None            # kernel changed since
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
-    assert bench.measured_traffic("c2", "f64", 48, 4, 80) is None
+    assert bench.measured_traffic("W", "mixed_f32") is None
 
 
 def test_committed_record_describes_the_headline_launch():
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        pytest.skip("no counter record of the batch kernel committed")
     with open(bench.TRAFFIC_FILE) as fh:
         rec = json.load(fh)
-    assert (rec["config"], rec["precision"]) == ("c2", "f64")
+    probs = batch_instances(256, seed=5, dt=2.5e-5)
+    assert rec["workload"] == bench.batch_workload(probs, 2.5e-5, 32)
+    assert rec["precision"] == "mixed_f32"
     assert rec["traffic_bytes_per_launch"] > 0 and len(rec["kernel_sources_sha256"]) == 64
+
+
+def _walk_projection(p, m, s_x, sets):
+    """Bytes of one projection of size m walked pass by pass: v_1 written, then per Arnoldi
+    step j one operator apply (x, y, M^-1/2 and `sets` linearisation fields of 3n values,
+    connectivity), reads of v_1..v_j and one write, then the combination (m reads)."""
+    n3 = 3 * p.n_nodes
+    L = 2 * p.n_free + 1
+    apply_bytes = (2 * n3 + n3 + sets * n3) * s_x + 32 * p.n_elems
+    total = L * 8
+    for j in range(1, m + 1):
+        total += apply_bytes + j * L * 8 + L * 8
+    return total + m * L * 8
 
 
 @pytest.mark.parametrize("m", [1, 5, 48])
 def test_algorithmic_bytes_counts_each_vector_pass(m):
-    """Basis traffic counted by walking the projection: the initial read of w and write of
-    v_1, then per Arnoldi step j one operator apply, reads of v_1..v_j and one write, then the
-    combination (m reads, one write)."""
     p = config("c1")
-    n3 = 3 * p.n_nodes
-    L = 2 * n3 + 1
-    apply_bytes = (2 * n3 + 2 * n3 + n3 + n3) * 8 + 32 * p.n_elems   # x, y, M^-1/2, load, conn
-    total = 2 * L * 8                                                 # w read, v_1 written
-    for j in range(1, m + 1):
-        total += apply_bytes + j * L * 8 + L * 8
-    total += m * L * 8 + L * 8
+    total = _walk_projection(p, m, 8, 0)
     assert bench.algorithmic_bytes(p, m, 1) == total
     assert bench.algorithmic_bytes(p, m, 3, projections=2) == 6 * total
+
+
+def test_batch_bytes_sum_both_projections_of_every_instance():
+    probs = batch_instances(3, seed=5, dt=2.5e-5)
+    per = [(10, 1, 8, 1), (12, 2, 9, 1), (11, 1, 7, 2)]
+    ref = sum(kc * _walk_projection(p, mc, 4, 1) + kp * _walk_projection(p, mp, 4, 2)
+              for p, (mc, kc, mp, kp) in zip(probs, per))
+    assert bench.batch_algorithmic_bytes(probs, per, 4) == ref
