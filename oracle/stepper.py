@@ -44,8 +44,13 @@ class Propagator:
         self.Mih = 1.0 / np.sqrt(M)
         self.P0bar = self.Mih * traction_load(prob.xyz, prob.faces, prob.t0)[self.free]
         self.linear = prob.model == "linear"
-        if s0 is None:
-            unloaded = (not np.any(self.P0bar)) or (not np.any(np.asarray(prob.knots_s)))
+        unloaded = (not np.any(self.P0bar)) or (not np.any(np.asarray(prob.knots_s)))
+        # s0 = "scaled": the augmented entry at the problem's own scale (reading of the
+        # augmented form, whose exact propagation does not depend on s0 while the stopping
+        # rule eps <= tol ||wbar|| does), s0 = max(||[ubar; vbar]||, dt ||Pbar_0|| max |scale|),
+        # fixed at the first step when dt is known
+        self.s0_scaled = (s0 == "scaled") and not unloaded
+        if s0 is None or s0 == "scaled":
             s0 = 0.0 if unloaded else 1.0
         self.kw = dict(tol=prob.tol if tol is None else tol, m_max=m_max, check_every=check_every,
                        m_fixed=m_fixed, k_fixed=k_fixed, max_substeps=max_substeps)
@@ -102,6 +107,11 @@ class Propagator:
     def step(self, dt: float):
         N = self.N
         t = self.t
+        if self.s0_scaled:
+            self.s0_scaled = False
+            smax = float(np.abs(np.asarray(self.prob.knots_s)).max())
+            self.s0 = max(float(np.linalg.norm(np.concatenate([self.ubar, self.vbar]))),
+                          dt * float(np.linalg.norm(self.P0bar)) * smax)
         w = np.concatenate([self.ubar, self.vbar, [self.s0]])
         rec = {}
         if self.linear:

@@ -230,3 +230,34 @@ def test_predictor_extrapolates_H_to_the_quarter_step():
         errs.append(np.linalg.norm(Hp - Href) / np.linalg.norm(Href))
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 1.7), (errs, orders)
+
+
+def test_augmented_entry_scale_does_not_change_the_propagation():
+    """Sec. 2.3's augmented form: A's last column is Pbar / s0 and the entry stays s0, so the
+    exact propagation of [ubar; vbar] does not depend on s0 (dense exp(dt A) for s0 = 1 and
+    s0 = 1e-5 agree to rounding).  The Krylov stopping rule eps <= tol ||wbar|| does: on a
+    lightly loaded beam whose state is far below 1 in SI units, the scaled entry
+    (s0 = dt ||Pbar_0||) reaches the dense result to ~tol relative, s0 = 1 does not."""
+    import scipy.linalg
+    p = config("c1", dt=1e-5).with_(t0=np.array([0.0, 0.0, -1.0e2]))
+    N = None
+    outs = {}
+    for s0 in (1.0, 1e-5):
+        pr = Propagator(p, tol=1e-10, m_max=64, s0=s0)
+        N = pr.N
+        A = np.zeros((2 * N + 1, 2 * N + 1))
+        for c in range(2 * N + 1):
+            e = np.zeros(2 * N + 1)
+            e[c] = 1.0
+            A[:, c] = pr.A_apply(e, 1.0, None, pr.P0bar)
+        w = np.concatenate([pr.ubar, pr.vbar, [s0]])
+        outs[s0] = scipy.linalg.expm(p.dt * A) @ w
+    ref = outs[1.0][:2 * N]
+    assert np.abs(outs[1e-5][:2 * N] - ref).max() <= 1e-12 * np.abs(ref).max()
+    errs = {}
+    for s0 in (1.0, "scaled"):
+        pr = Propagator(p, tol=1e-10, m_max=64, s0=s0)
+        pr.step(p.dt)
+        errs[s0] = np.abs(np.concatenate([pr.ubar, pr.vbar]) - ref).max() / np.abs(ref).max()
+    assert errs["scaled"] < 1e-6          # measured 5.2e-8 (the estimate sits below the error)
+    assert errs[1.0] > 100 * errs["scaled"]  # measured 5.8e-4
