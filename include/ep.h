@@ -129,8 +129,16 @@ ep_status ep_set_traction(ep_ctx* ctx, int64_t n_faces, const int32_t* face_node
  * exactly m_fixed steps (the paper's fixed-m production mode, Sec. 6.2); k_fixed > 0:
  * exactly k_fixed substeps; max_substeps: unconverged projections are redone with
  * 2, 4, ... substeps of the same frozen operator up to this count, then EP_ERR_KRYLOV.
- * s0: value of the augmented entry of wbar (negative = automatic: 1 with a load, 0
- * without, which is the paper's 2N form for P = 0). */
+ * s0: value of the augmented entry of wbar.  EP_S0_AUTO (or any other negative value except
+ * EP_S0_SCALED): 1 with a load, 0 without, which is the paper's 2N form for P = 0.
+ * EP_S0_SCALED: the entry at the problem's own scale, s0 = max(||[ubar; vbar]||_2,
+ * dt ||Pbar_0||_2 max_k |scale_k|), fixed per instance at the first ep_step / ep_batch_step
+ * after its state is set (0 without a load).  The exact propagation does not depend on s0
+ * (A's last column is Pbar / s0); the stopping rule does, since ||wbar|| includes s0: with
+ * s0 = 1 and a state far below 1 in SI units the Krylov error is not small relative to the
+ * state.  s0 >= 0: that value. */
+#define EP_S0_AUTO (-1.0)
+#define EP_S0_SCALED (-2.0)
 ep_status ep_set_krylov(ep_ctx* ctx, double tol, int m_max, int check_every, int m_fixed,
                         int k_fixed, int max_substeps, double s0);
 

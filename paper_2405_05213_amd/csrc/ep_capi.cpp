@@ -65,6 +65,7 @@ struct Inst {
   int hist_new = -1, hist_old = -1;
   int nhist = 0;
   bool state_set = false;
+  bool s0_pending = false;      // scaled s0: resolved at the next step (needs dt)
 };
 
 }  // namespace
@@ -324,6 +325,33 @@ static double auto_s0(const ep_ctx* c, const Inst& I) {
   bool nonzero_scale = false;
   for (int i = 0; i < I.n_knots; ++i) nonzero_scale |= I.knots[I.n_knots + i] != 0.0;
   return (load && nonzero_scale) ? 1.0 : 0.0;
+}
+
+// Scaled augmented entry (ep_set_krylov with s0 = EP_S0_SCALED): the augmented entry of wbar is
+// taken at the problem's own scale, s0 = max(||[ubar; vbar]||_2, dt ||Pbar_0||_2 max_k |scale_k|),
+// fixed at the first step after a state is set (when dt is known).  The exact propagation does
+// not depend on s0; the stopping rule eps <= tol ||wbar|| does, and with s0 = 1 it is loose
+// for states far smaller than one in SI units.  Stays 0 without a load.
+static bool scaled_s0_mode(const ep_ctx* c) { return c->s0_user == EP_S0_SCALED; }
+
+static ep_status resolve_s0(ep_ctx* c, Inst& I, double dt) {
+  if (!I.s0_pending) return EP_OK;
+  I.s0_pending = false;
+  if (I.M.s0 == 0.0) return EP_OK;              // unloaded: the 2N form
+  std::vector<double> w(2 * (size_t)I.n3), pb((size_t)I.n3);
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  EP_HIP(c, hipMemcpy(w.data(), dptr<double>(c, I.o_S), 8 * w.size(), hipMemcpyDeviceToHost));
+  EP_HIP(c, hipMemcpy(pb.data(), I.M.p0bar, 8 * pb.size(), hipMemcpyDeviceToHost));
+  double nw = 0.0, np = 0.0, smax = 0.0;
+  for (double x : w) nw += x * x;
+  for (double x : pb) np += x * x;
+  for (int i = 0; i < I.n_knots; ++i) smax = std::max(smax, std::fabs(I.knots[I.n_knots + i]));
+  const double s0 = std::max(std::sqrt(nw), dt * std::sqrt(np) * smax);
+  if (!(s0 > 0.0) || !std::isfinite(s0)) return EP_OK;
+  I.M.s0 = s0;
+  I.M.s_inv = 1.0 / s0;
+  EP_HIP(c, hipMemcpy(dptr<double>(c, I.o_S) + 2 * (size_t)I.n3, &s0, 8, hipMemcpyHostToDevice));
+  return EP_OK;
 }
 
 // A structured box: node (i, j, k) = i + (nx+1)(j + (ny+1)k), elements in i-fastest order
@@ -828,6 +856,7 @@ ep_status ep_set_state(ep_ctx* c, double t, const double* u, const double* v) {
   I.nhist = 0;
   I.hist_new = I.hist_old = -1;
   I.state_set = true;
+  I.s0_pending = scaled_s0_mode(c);
   return EP_OK;
 }
 
@@ -836,6 +865,10 @@ ep_status ep_step(ep_ctx* c, double dt, int64_t n) {
   if (s != EP_OK) return s;
   if (!c->one.state_set) return fail(c, EP_ERR_ORDER, "call ep_set_state first");
   if (!(dt > 0.0) || !std::isfinite(dt) || n < 0) return fail(c, EP_ERR_ARG, "need dt > 0 and n_steps >= 0");
+  if (n > 0) {
+    s = resolve_s0(c, c->one, dt);
+    if (s != EP_OK) return s;
+  }
   for (int64_t i = 0; i < n; ++i) {
     s = step_one(c, c->one, dt);
     if (s != EP_OK) return s;
@@ -1270,6 +1303,7 @@ ep_status ep_batch_set_state(ep_ctx* c, int32_t id, double t, const double* u, c
                            c->stream));
   EP_HIP(c, hipStreamSynchronize(c->stream));
   I.state_set = true;
+  I.s0_pending = scaled_s0_mode(c);
   return EP_OK;
 }
 
@@ -1289,6 +1323,18 @@ ep_status ep_batch_step(ep_ctx* c, double dt, int64_t n) {
   for (auto& I : c->insts)
     if (!I.state_set) return fail(c, EP_ERR_ORDER, "every instance needs ep_batch_set_state");
   if (n == 0) return EP_OK;
+  for (int32_t id = 0; id < (int32_t)c->insts.size(); ++id) {
+    Inst& I = c->insts[id];
+    if (!I.s0_pending) continue;
+    ep_status s = resolve_s0(c, I, dt);
+    if (s != EP_OK) return s;
+    s = pull_record(c, id);
+    if (s != EP_OK) return s;
+    c->btab[id].M.s0 = I.M.s0;
+    c->btab[id].M.s_inv = I.M.s_inv;
+    EP_HIP(c, hipMemcpy(dptr<BatchInst>(c, c->o_batch_tab) + id, &c->btab[id], sizeof(BatchInst),
+                        hipMemcpyHostToDevice));
+  }
   // one step = one launch per material model present, captured once into a graph and replayed
   if (c->bgraph == nullptr || c->bgraph_dt != dt) {
     if (c->bgraph) { (void)hipGraphExecDestroy(c->bgraph); c->bgraph = nullptr; }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libep.so")
 EP_OK, EP_ERR_ARG, EP_ERR_ORDER, EP_ERR_HIP, EP_ERR_KRYLOV = 0, -1, -2, -3, -4
 EP_ERR_INVERTED, EP_ERR_NONFINITE, EP_ERR_WORKSPACE, EP_ERR_DEVICE = -5, -6, -7, -8
 MODELS = {"linear": 0, "nh": 1, "yeoh": 2, "svk": 3}
+S0_AUTO, S0_SCALED = -1.0, -2.0          # ep_set_krylov's s0 modes (include/ep.h)
 PRECISIONS = {"f64": 0, "mixed_f32": 1, "mixed_bf16": 2}
 
 _i64, _i32, _dbl, _vp = C.c_int64, C.c_int32, C.c_double, C.c_void_p

@@ -18,6 +18,8 @@ def pair(prob, **kw):
     okw = {k: kw[k] for k in ("tol", "m_max", "check_every", "m_fixed", "k_fixed", "max_substeps") if k in kw}
     if "s0" in kw and kw["s0"] >= 0:
         okw["s0"] = kw["s0"]
+    elif "s0" in kw and kw["s0"] == epmod.S0_SCALED:
+        okw["s0"] = "scaled"
     ctx = epmod.solver_from_problem(prob, **kw)
     orc = Propagator(prob, **okw)
     return ctx, orc

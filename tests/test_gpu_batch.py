@@ -90,3 +90,26 @@ def test_batch_mixed_f32_matches_oracle():
             eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
             say(f"  instance {i} {p.name} model={p.model} nodes={p.n_nodes} dt={dt}: rel err u {eu:.2e} v {ev:.2e}")
             assert eu < 5e-6 and ev < 5e-6
+
+
+def test_batch_scaled_s0_matches_oracle():
+    """Augmented entry at the problem's scale (ep_set_krylov s0 = EP_S0_SCALED): each instance
+    fixes s0 = max(||[ubar; vbar]||, dt ||Pbar_0|| max |scale|) at its first step; the oracle
+    applies the same rule.  Small steps of lightly loaded blocks, where s0 = 1 would leave the
+    Krylov error large relative to the state."""
+    from paper_2405_05213_amd import batch_from_problems
+    from paper_2405_05213_amd.ep import S0_SCALED
+    probs = batch_instances(n_inst=4, seed=11, dt=1.25e-5, nx_range=(6, 10), nyz_range=(2, 3))
+    probs = [p.with_(t0=p.t0 * 0.1) for p in probs]
+    say(f"[batch] scaled s0, {len(probs)} instances")
+    b = batch_from_problems(probs, m_max=32, s0=S0_SCALED)
+    n = 8
+    b.step(probs[0].dt, n)
+    for i, p in enumerate(probs):
+        t, u, v = b.get_state(i)
+        orc = Propagator(p, m_max=32, s0="scaled")
+        orc.run(p.dt, n)
+        eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
+        say(f"  instance {i}: s0 = {orc.s0:.3e}, err u {eu:.2e} v {ev:.2e}")
+        assert eu < 1e-8 and ev < 1e-8
+        assert b.stats(i)["m"] == orc.log[-1]["corr"]["m"][-1]

@@ -323,3 +323,22 @@ def test_autotune_keeps_state_and_parity(name, over):
     t, u, v = ctx.get_state()
     orc.run(p.dt, 5)
     assert maxrel(u, orc.u()) < 1e-8 and maxrel(v, orc.v()) < 1e-8
+
+
+@pytest.mark.parametrize("model,name,over", [("nh", "c3", dict(nx=8, ny=2, nz=2, dt=1e-4)),
+                                              ("linear", "c1", dict(dt=1e-5))])
+def test_scaled_s0_matches_oracle(model, name, over):
+    """ep_set_krylov with s0 = EP_S0_SCALED (augmented entry at the problem's scale, fixed at the
+    first step) against the oracle with the same rule, adaptive subspace."""
+    from paper_2405_05213_amd.ep import S0_SCALED
+    say(f"[steps] scaled s0 {model} {name} {over}")
+    p = config(name, **over)
+    ctx, orc = pair(p, m_max=48, s0=S0_SCALED)
+    n = 10
+    ctx.step(p.dt, n)
+    orc.run(p.dt, n)
+    t, u, v = ctx.get_state()
+    eu, ev = maxrel(u, orc.u()), maxrel(v, orc.v())
+    say(f"  s0 = {orc.s0:.3e}, err u {eu:.2e} v {ev:.2e}")
+    assert eu < 1e-8 and ev < 1e-8
+    assert np.array_equal(ctx.step_log(n)["m_corr"], np.array([r["corr"]["m"][0] for r in orc.log]))
