@@ -243,15 +243,16 @@ def config(name: str, **over) -> Problem:
     return p
 
 
-def batch_instances(n_inst: int = 256, seed: int = 5, dt: float = 2.5e-5,
+def batch_instances(n_inst: int = 256, seed: int = 5, dt: float = 6.25e-6,
                     n_steps: int = 1000, nx_range=(20, 60), nyz_range=(4, 8),
                     h: float = 0.01) -> list:
     """c5: independent rubber blocks of uneven size.
 
     nx ~ U{20..60}, ny = nz ~ U{4..8} (drawn jointly), cubic cells of edge h;
     compressible Neo-Hookean with mu ~ U[0.2, 1] MPa, lambda = 5 mu, rho 1100;
-    x = 0 clamped, constant tip traction (-z) ~ U[1e3, 1e4] Pa, at rest.  dt = 2.5e-5 s keeps the
-    relative energy error of every instance below 1e-6 (at 1e-4 s some instances reach 5e-6).
+    x = 0 clamped, constant tip traction (-z) ~ U[1e3, 1e4] Pa, at rest.  dt = 6.25e-6 s (1e-4
+    halved four times) keeps the relative energy error of every instance below 1e-6 over the
+    1000 steps (with the augmented entry at each block's scale; 1.25e-5 s reaches 1.4e-6).
     """
     rng = np.random.default_rng(seed)
     out = []
