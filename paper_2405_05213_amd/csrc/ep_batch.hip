@@ -21,82 +21,108 @@ static __device__ __forceinline__ int free_slot(int a, int b) {
   return 0;
 }
 
-// One step of one instance (Sec. 4.1-4.2); returns false after a sticky error.
+// One step of one instance (Sec. 4.1-4.2); returns false after a sticky error.  B (the
+// instance record) and a (the projection arguments) live in LDS: thread 0 writes them, a
+// workgroup barrier publishes them, every lane reads them (per-lane copies of these records
+// would live in scratch memory).
 template <typename T, int MODEL, class Team>
-__device__ bool device_step(Team& tm, BatchInst& B, const KrylovCfg& cfg, double dt, double* lw, double* lv,
-                            double* red, double* yb, int* flag, const KLds& X) {
-  ExpvArgs a;
-  a.M = B.M;
-  a.W = B.W;
-  a.cfg = cfg;
-  a.log_idx = (int)(B.step_idx % kLogSteps);
+__device__ bool device_step(Team& tm, BatchInst& B, ExpvArgs& a, const KrylovCfg& cfg, double dt, double* lw,
+                            double* lv, double* red, double* yb, int* flag, const KLds& X) {
+  const bool w0 = threadIdx.x == 0;
   const double t = B.t;
   const int n3 = B.M.n3;
+  if (w0) {
+    a.M = B.M;
+    a.W = B.W;
+    a.cfg = cfg;
+    a.log_idx = (int)(B.step_idx % kLogSteps);
+  }
   if (MODEL == kLinear) {
-    a.op.tau = dt;
-    a.op.t_eval = t + 0.5 * dt;
-    a.op.nsets = 0;
-    a.kind = 0;
-    a.x_in = B.S;
-    a.x_out = B.S;
-    a.out_mode = 0;
+    if (w0) {
+      a.op = OpArgs{};
+      a.op.tau = dt;
+      a.op.t_eval = t + 0.5 * dt;
+      a.op.nsets = 0;
+      a.kind = 0;
+      a.x_in = B.S;
+      a.x_out = B.S;
+      a.out_mode = 0;
+    }
+    __syncthreads();
     expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag, X);
   } else {
-    OpArgs pred{};
-    pred.tau = 0.5 * dt;
-    pred.t_eval = t + 0.25 * dt;
+    const int nhist = B.nhist, hnew = B.hist_new, hold = B.hist_old;
     int reserve = -1;
-    if (B.nhist == 0) {
-      const int s0 = free_slot(B.hist_new, B.hist_old);
-      team_get_u(tm, B.M, B.S, B.hist + (size_t)s0 * n3, flag);
-      pred.nsets = 1;
-      pred.ulin[0] = B.hist + (size_t)s0 * n3;
-      pred.wts[0] = 1.0;
-      reserve = s0;
-    } else if (B.nhist == 1) {
-      pred.nsets = 1;
-      pred.ulin[0] = B.hist + (size_t)B.hist_new * n3;
-      pred.wts[0] = 1.0;
-    } else {
-      pred.nsets = 2;
-      pred.ulin[0] = B.hist + (size_t)B.hist_new * n3;
-      pred.wts[0] = 1.75;
-      pred.ulin[1] = B.hist + (size_t)B.hist_old * n3;
-      pred.wts[1] = -0.75;
+    if (nhist == 0) {
+      reserve = free_slot(hnew, hold);
+      team_get_u(tm, B.M, B.S, B.hist + (size_t)reserve * n3, flag);
     }
-    const int snew = free_slot(B.hist_new, reserve >= 0 ? reserve : B.hist_old);
-    a.op = pred;
-    a.kind = 1;
-    a.x_in = B.S;
-    a.x_out = B.hist + (size_t)snew * n3;
-    a.out_mode = 1;
+    const int snew = free_slot(hnew, reserve >= 0 ? reserve : hold);
+    if (w0) {
+      OpArgs pred{};
+      pred.tau = 0.5 * dt;
+      pred.t_eval = t + 0.25 * dt;
+      if (nhist == 0) {
+        pred.nsets = 1;
+        pred.ulin[0] = B.hist + (size_t)reserve * n3;
+        pred.wts[0] = 1.0;
+      } else if (nhist == 1) {
+        pred.nsets = 1;
+        pred.ulin[0] = B.hist + (size_t)hnew * n3;
+        pred.wts[0] = 1.0;
+      } else {
+        pred.nsets = 2;
+        pred.ulin[0] = B.hist + (size_t)hnew * n3;
+        pred.wts[0] = 1.75;
+        pred.ulin[1] = B.hist + (size_t)hold * n3;
+        pred.wts[1] = -0.75;
+      }
+      a.op = pred;
+      a.kind = 1;
+      a.x_in = B.S;
+      a.x_out = B.hist + (size_t)snew * n3;
+      a.out_mode = 1;
+    }
+    __syncthreads();
     expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag, X);
     if (tm.dead || read_err(&B.W.ctrl->err) != 0) return false;
-    OpArgs corr{};
-    corr.tau = dt;
-    corr.t_eval = t + 0.5 * dt;
-    corr.nsets = 1;
-    corr.ulin[0] = B.hist + (size_t)snew * n3;
-    corr.wts[0] = 1.0;
-    a.op = corr;
-    a.kind = 0;
-    a.x_in = B.S;
-    a.x_out = B.S;
-    a.out_mode = 0;
+    __syncthreads();                             // every lane is done reading a
+    if (w0) {
+      OpArgs corr{};
+      corr.tau = dt;
+      corr.t_eval = t + 0.5 * dt;
+      corr.nsets = 1;
+      corr.ulin[0] = B.hist + (size_t)snew * n3;
+      corr.wts[0] = 1.0;
+      a.op = corr;
+      a.kind = 0;
+      a.x_in = B.S;
+      a.x_out = B.S;
+      a.out_mode = 0;
+    }
+    __syncthreads();
     expv_body<T, MODEL>(tm, a, lw, lv, red, yb, flag, X);
-    if (B.nhist == 0) {
-      B.hist_old = -1;
-      B.hist_new = snew;
-      B.nhist = 1;
-    } else {
-      B.hist_old = B.hist_new;
-      B.hist_new = snew;
-      B.nhist = 2;
+    __syncthreads();                             // every lane is done reading B and a
+    if (w0) {
+      if (nhist == 0) {
+        B.hist_old = -1;
+        B.hist_new = snew;
+        B.nhist = 1;
+      } else {
+        B.hist_old = hnew;
+        B.hist_new = snew;
+        B.nhist = 2;
+      }
     }
   }
-  if (tm.dead || read_err(&B.W.ctrl->err) != 0) return false;
-  B.t = t + dt;
-  B.step_idx += 1;
+  const bool failed = tm.dead || read_err(&B.W.ctrl->err) != 0;
+  __syncthreads();
+  if (failed) return false;
+  if (w0) {
+    B.t = t + dt;
+    B.step_idx += 1;
+  }
+  __syncthreads();
   return true;
 }
 
@@ -113,10 +139,15 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
   // the slice region (lds_slices doubles) doubles as expm scratch: the sequential form
   // reloads both slice buffers after a check point
   const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, true};
-  if (threadIdx.x == 0) *flag = 1;
-  __syncthreads();
+  // the instance record and the projection arguments: one copy per workgroup in LDS
+  __shared__ BatchInst B;
+  __shared__ ExpvArgs a;
   const int id = ids[blockIdx.x];
-  BatchInst B = tab[id];
+  if (threadIdx.x == 0) {
+    *flag = 1;
+    B = tab[id];
+  }
+  __syncthreads();
   double* lw;
   double* lv;
   if (B.use_lds) {
@@ -128,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
   }
   BlockTeam tm;
   for (int s = 0; s < n_steps; ++s)
-    if (!device_step<T, MODEL>(tm, B, cfg, dt, lw, lv, red, yb, flag, X)) break;
+    if (!device_step<T, MODEL>(tm, B, a, cfg, dt, lw, lv, red, yb, flag, X)) break;
   if (threadIdx.x == 0) {
     tab[id].t = B.t;
     tab[id].step_idx = B.step_idx;
@@ -138,6 +169,9 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
   }
 }
 
+// dynamic LDS of the batch kernel (its static LDS, the record and arguments, comes on top:
+// sizeof(BatchInst) + sizeof(ExpvArgs) = 864 bytes, within the 160 KB beside the largest
+// dynamic part, 2 * 9984 + 304 doubles)
 size_t batch_lds_bytes(int max_lds_chunk) { return (size_t)(kBatchHead + 2 * max_lds_chunk) * sizeof(double); }
 
 static const void* batch_kernel(int prec, int model) {

@@ -245,6 +245,95 @@ __device__ __forceinline__ bool secant_coeffs(const T (&D)[3][3], const double* 
   return true;
 }
 
+// P += w * Phi(D, X) for the Neo-Hookean or Yeoh solid in one pass, the coefficients used
+// as soon as they are formed (fewer values live at once than secant_coeffs + secant_apply):
+//   W : X = -(a/3)(2 tr X + D : X) + b (P_e : X)     (Yeoh; NH: lambda l(J) (P_e : X))
+//   Fi = F^{-1}, Ci = Fi Fi^T, Y = X Ci, Z = X Fi + Y = X N, X S = X Ci Sigma = Y Sigma
+//   P += w [a (Z + Z^T) / 2 + (W : X) Ci + Y Sigma].
+// Returns false if J <= 0 (or not finite).
+template <typename T, int MODEL>
+__device__ __forceinline__ bool secant_stress_add(const T (&D)[3][3], const T (&X)[3][3], const double* mp, T w,
+                                                  T (&P)[3][3]) {
+  T c[3][3];
+  c[0][0] = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+  c[0][1] = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+  c[0][2] = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+  c[1][0] = D[0][2] * D[2][1] - D[0][1] * D[2][2];
+  c[1][1] = D[0][0] * D[2][2] - D[0][2] * D[2][0];
+  c[1][2] = D[0][1] * D[2][0] - D[0][0] * D[2][1];
+  c[2][0] = D[0][1] * D[1][2] - D[0][2] * D[1][1];
+  c[2][1] = D[0][2] * D[1][0] - D[0][0] * D[1][2];
+  c[2][2] = D[0][0] * D[1][1] - D[0][1] * D[1][0];
+  const T trD = D[0][0] + D[1][1] + D[2][2];
+  T x = T(0), pex = T(0), dx = T(0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T pe = (i == k ? T(1) + T(0.5) * trD : T(0)) - T(0.5) * D[k][i] + c[i][k] * T(1.0 / 3.0);
+      x += pe * D[i][k];
+      pex += pe * X[i][k];
+      dx += D[i][k] * X[i][k];
+    }
+  const T J = T(1) + x;
+  if (!(J > T(0))) return false;
+  const T trX = X[0][0] + X[1][1] + X[2][2];
+  const T Jinv = T(1) / J;
+  T Fi[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Fi[i][k] = (c[k][i] + (i == k ? T(1) + trD : T(0)) - D[i][k]) * Jinv;
+  T Ci[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = i; k < 3; ++k)
+      Ci[sym_idx(i, k)] = Fi[i][0] * Fi[k][0] + Fi[i][1] * Fi[k][1] + Fi[i][2] * Fi[k][2];
+  T Y[3][3], Z[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Y[i][k] = X[i][0] * Ci[sym_idx(0, k)] + X[i][1] * Ci[sym_idx(1, k)] + X[i][2] * Ci[sym_idx(2, k)];
+      Z[i][k] = Y[i][k] + X[i][0] * Fi[0][k] + X[i][1] * Fi[1][k] + X[i][2] * Fi[2][k];
+    }
+  T E2[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = i; k < 3; ++k)
+      E2[sym_idx(i, k)] = D[i][k] + D[k][i] + D[0][i] * D[0][k] + D[1][i] * D[1][k] + D[2][i] * D[2][k];
+  T a, wx, sd, sg;         // Sigma = sg E2 + sd I
+  if (MODEL == kNH) {
+    const T mu = T(mp[0]), lam = T(mp[1]);
+    const T l = log_ratio(x);
+    a = mu;
+    wx = lam * l * pex;
+    sg = mu;
+    sd = lam * l * x;
+  } else {
+    const T C10 = T(mp[0]), C20 = T(mp[1]), C30 = T(mp[2]), D1 = T(mp[3]);
+    const T Jm23 = j_pow_m23(J, x);
+    const T trE2 = E2[0] + E2[1] + E2[2];
+    const T z = (T(3) + trE2) * Jm23 - T(3);
+    a = T(2) * Jm23 * (C10 + T(2) * C20 * z + T(3) * C30 * z * z);
+    const T beta = T(2) / D1 * J;
+    wx = -(a * T(1.0 / 3.0)) * (T(2) * trX + dx) + beta * pex;
+    sg = a;
+    sd = beta * x - a * trE2 * T(1.0 / 3.0);
+  }
+  const T ah = T(0.5) * w * a, bw = w * wx, ws = w * sg, wd = w * sd;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const T ys = Y[i][0] * E2[sym_idx(0, k)] + Y[i][1] * E2[sym_idx(1, k)] + Y[i][2] * E2[sym_idx(2, k)];
+      P[i][k] += ah * (Z[i][k] + Z[k][i]) + bw * Ci[sym_idx(i, k)] + ws * ys + wd * Y[i][k];
+    }
+  return true;
+}
+
 // P += w * [a sym(X N) + (W : X) Ci + X S]
 template <typename T>
 __device__ __forceinline__ void secant_apply(const Secant<T>& s, T w, const T (&X)[3][3], T (&P)[3][3]) {
@@ -428,14 +517,11 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
         }
       } else if (MODEL != kLinear) {
         T Du[3][3];
-        Secant<T> sc;
         grad_at(Q, u0, Jinv, Du);
-        ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
-        secant_apply(sc, T(op.wts[0]), X, S);
+        ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[0]), S);
         if (nsets >= 2) {
           grad_at(Q, u1, Jinv, Du);
-          ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
-          secant_apply(sc, T(op.wts[1]), X, S);
+          ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[1]), S);
         }
       }
     }
@@ -543,10 +629,8 @@ __device__ __forceinline__ bool elem_force_qp(const Mesh& M, const OpArgs& op, i
     } else if (MODEL != kLinear) {
       for (int s = 0; s < nsets; ++s) {
         T Du[3][3];
-        Secant<T> sc;
         grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
-        ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
-        secant_apply(sc, T(op.wts[s]), X, S);
+        ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[s]), S);
       }
     }
   }
