@@ -144,6 +144,19 @@ ep_status ep_set_krylov(ep_ctx* ctx, double tol, int m_max, int check_every, int
 
 ep_status ep_set_precision(ep_ctx* ctx, ep_precision prec);
 
+/* Time integrator (before ep_bind_workspace; single-instance contexts):
+ *   2 (default): the paper's second-order step, the Magnus series truncated after its first
+ *     term at the step midpoint, with the predictor-corrector of Sec. 4.2 for nonlinear H;
+ *   4: the series truncated after two terms (Sec. 3.3 remark), the two-point Gauss-Legendre
+ *     rule at t + (1/2 -+ sqrt(3)/6) dt: Omega = dt/2 (A_1 + A_2) - sqrt(3) dt^2/12 [A_1, A_2],
+ *     one Krylov projection of exp(Omega) wbar per step, each Arnoldi step applying both
+ *     H-matrices to the u- and v-parts of the vector; H at the displacements predicted for the
+ *     nodes by cubic Hermite extrapolation of this and the previous step's start state (first
+ *     step after ep_set_state: u + s v + s^2/2 M^{-1}(P - R(u))).  Fourth order in dt.
+ * EP_ERR_ARG for another order, and at ep_bind_workspace for a batch, EP_PREC_MIXED_BF16, or a
+ * team whose Krylov slices do not fit in LDS. */
+ep_status ep_set_scheme(ep_ctx* ctx, int order);
+
 /* Form of the Arnoldi modified Gram-Schmidt loop (Sec. 4.3) in the single-instance kernel,
  * set before ep_bind_workspace.  mode 0: sequential, one team reduction per inner
  * product (j + 1 in step j).  mode 1: compact WY, the same recurrence written as the

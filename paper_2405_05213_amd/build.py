@@ -15,8 +15,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libep.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["ep_kernels.hip", "ep_expv_global.hip", "ep_batch.hip", "ep_tangent.hip", "ep_noalloc.hip",
-           "ep_capi.cpp"]
+SOURCES = ["ep_kernels.hip", "ep_expv_global.hip", "ep_expv_m4.hip", "ep_batch.hip", "ep_tangent.hip",
+           "ep_noalloc.hip", "ep_capi.cpp"]
 ARCH = os.environ.get("EP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
@@ -45,7 +45,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -55,7 +55,7 @@ struct Inst {
   size_t o_xyz, o_conn, o_incp, o_inc, o_geo, o_geo32, o_vdet, o_mih, o_mh, o_p0, o_p0bar, o_faces, o_fincp,
       o_finc, o_ff, o_knots, o_clamp, o_S, o_X, o_Wun, o_V, o_F, o_F32, o_hist, o_stage, o_slots, o_H, o_Escr, o_y, o_ke,
       o_stencil,
-      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr, o_psi, o_kst;
+      o_ctrl, o_log, o_pe, o_pv, o_eout, o_flags, o_wscr, o_psi, o_kst, o_F2, o_F2_32, o_Sprev;
   Mesh M{};
   bool kst_rest = false;       // the stored tangents are those of the rest-state operator
   KWork W{};
@@ -66,6 +66,8 @@ struct Inst {
   int nhist = 0;
   bool state_set = false;
   bool s0_pending = false;      // scaled s0: resolved at the next step (needs dt)
+  bool m4_prev = false;         // fourth-order scheme: the previous step's start state is in o_Sprev
+  double t_prev = 0.0;
 };
 
 }  // namespace
@@ -273,6 +275,10 @@ static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
   I.o_stencil = L.take(8 * 27 * 9);
   I.o_psi = L.take(2 * (size_t)kPsiValues);
   I.o_kst = L.take(c->cfg.prec == 2 ? 2 * kst_values((long long)ne) : 0);
+  const bool m4 = c->cfg.scheme == 4;
+  I.o_F2 = L.take(m4 ? 8 * 24 * ne : 0);
+  I.o_F2_32 = L.take(m4 ? 4 * 24 * ne : 0);
+  I.o_Sprev = L.take(m4 ? 8 * 2 * n3 : 0);
 }
 
 static int Gmax_of(const ep_ctx* c) { return std::max(1, std::max(c->cus, c->G_user)); }
@@ -489,6 +495,8 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   W.X = dptr<double>(c, I.o_X);
   W.F = dptr<double>(c, I.o_F);
   W.F32 = dptr<float>(c, I.o_F32);
+  W.F2 = c->cfg.scheme == 4 ? dptr<double>(c, I.o_F2) : nullptr;
+  W.F2_32 = c->cfg.scheme == 4 ? dptr<float>(c, I.o_F2_32) : nullptr;
   W.flags = dptr<unsigned long long>(c, I.o_slots);
   W.ring = W.flags + std::max(Gslots, 1);
   W.vw = c->cfg.ortho == 1 ? 2 * c->cfg.m_max : 0;
@@ -529,6 +537,16 @@ static OpArgs op_linear(double tau, double t_eval) {
   return op;
 }
 
+static OpArgs op_from(const double* ulin, double tau, double t_eval) {
+  OpArgs op{};
+  op.tau = tau;
+  op.t_eval = t_eval;
+  op.nsets = ulin ? 1 : 0;
+  op.ulin[0] = ulin;
+  op.wts[0] = 1.0;
+  return op;
+}
+
 // EP_PREC_MIXED_BF16: the element tangents of the operator about to be applied, formed
 // before its projection (those of the rest-state operator are kept while they stay valid).
 static ep_status form_tangents(ep_ctx* c, Inst& I, const OpArgs& op) {
@@ -559,6 +577,22 @@ static ep_status run_expv(ep_ctx* c, Inst& I, const OpArgs& op, int kind, const 
   return EP_OK;
 }
 
+// load scale(t) on the host: piecewise linear through the knots, constant outside
+static double load_scale_host(const Inst& I, double t) {
+  const int n = I.n_knots;
+  if (n <= 0) return 0.0;
+  const double* kt = I.knots.data();
+  const double* ks = kt + n;
+  if (t <= kt[0]) return ks[0];
+  if (t >= kt[n - 1]) return ks[n - 1];
+  int lo = 0, hi = n - 1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (kt[mid] <= t) lo = mid; else hi = mid;
+  }
+  return ks[lo] + (t - kt[lo]) / (kt[hi] - kt[lo]) * (ks[hi] - ks[lo]);
+}
+
 static double* hist_slot(ep_ctx* c, Inst& I, int s) { return dptr<double>(c, I.o_hist) + (size_t)s * I.n3; }
 
 static int free_slot(const Inst& I) {
@@ -567,7 +601,55 @@ static int free_slot(const Inst& I) {
   return 0;
 }
 
+// One step of the fourth-order scheme: exp(Omega) wbar with Omega the two-term Magnus
+// exponent at the Gauss-Legendre nodes tau_{1,2} = t + (1/2 -+ sqrt(3)/6) dt (Sec. 3.3's
+// two-term truncation), the H-matrices at the displacements predicted for tau_1, tau_2:
+// cubic Hermite through the (u, v) of this and the previous step's start, or on the first
+// step (after a state is set) u + s v + s^2/2 M^{-1}(P(t) - R(u)), R(u) = H(u) u.
+static ep_status step_m4(ep_ctx* c, Inst& I, double dt) {
+  double* S = dptr<double>(c, I.o_S);
+  const double t = I.t;
+  const int log_idx = (int)(I.step_idx % kLogSteps);
+  const double g = std::sqrt(3.0) / 6.0;
+  OpArgs op{};
+  op.tau = 1.0;
+  op.t_eval = t + (0.5 - g) * dt;
+  op.t_eval2 = t + (0.5 + g) * dt;
+  op.dt4 = dt;
+  op.c4 = std::sqrt(3.0) * dt * dt / 12.0;
+  op.nsets = 0;
+  if (I.model != EP_LINEAR) {
+    double* u1 = hist_slot(c, I, 0);
+    double* u2 = hist_slot(c, I, 1);
+    double* R = hist_slot(c, I, 2);
+    double* st = dptr<double>(c, I.o_stage);
+    if (!I.m4_prev) {
+      launch_get_state(I.n3, I.M.mih, S, st, st + I.n3, c->stream);
+      launch_apply_H(I.M, op_from(st, 1.0, 0.0), 0, st, R, I.W.F, I.W.F32, &I.W.ctrl->err, c->stream);
+      EP_HIP(c, hipGetLastError());
+    }
+    launch_m4_predict(I.M, S, dptr<double>(c, I.o_Sprev), R, load_scale_host(I, t), t, I.t_prev, op.t_eval,
+                      op.t_eval2, I.m4_prev ? 0 : 1, u1, u2, c->stream);
+    EP_HIP(c, hipGetLastError());
+    op.nsets = 2;
+    op.ulin[0] = u1;
+    op.ulin[1] = u2;
+    op.wts[0] = op.wts[1] = 1.0;
+  }
+  // this step's start state feeds the next step's extrapolation
+  EP_HIP(c, hipMemcpyAsync(dptr<double>(c, I.o_Sprev), S, 8 * 2 * (size_t)I.n3, hipMemcpyDeviceToDevice,
+                           c->stream));
+  ep_status s = run_expv(c, I, op, 0, S, S, 0, log_idx);
+  if (s != EP_OK) return s;
+  I.m4_prev = true;
+  I.t_prev = t;
+  I.t = t + dt;
+  I.step_idx += 1;
+  return EP_OK;
+}
+
 static ep_status step_one(ep_ctx* c, Inst& I, double dt) {
+  if (c->cfg.scheme == 4) return step_m4(c, I, dt);
   double* S = dptr<double>(c, I.o_S);
   const double t = I.t;
   const int log_idx = (int)(I.step_idx % kLogSteps);
@@ -756,6 +838,14 @@ ep_status ep_get_orthogonalization(ep_ctx* c, int* mode) {
   return EP_OK;
 }
 
+ep_status ep_set_scheme(ep_ctx* c, int order) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "ep_set_scheme after ep_bind_workspace");
+  if (order != 2 && order != 4) return fail(c, EP_ERR_ARG, "the time integrator order must be 2 or 4");
+  c->cfg.scheme = order;
+  return EP_OK;
+}
+
 ep_status ep_set_precision(ep_ctx* c, ep_precision p) {
   if (!c) return EP_ERR_ARG;
   if (p != EP_PREC_F64 && p != EP_PREC_MIXED_F32 && p != EP_PREC_MIXED_BF16)
@@ -805,6 +895,9 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
   if (bytes < need) return fail(c, EP_ERR_WORKSPACE, "workspace too small");
   if (!is_gpu(c)) return fail(c, EP_ERR_HIP, "host-only context cannot bind device memory");
   EP_HIP(c, hipSetDevice(c->device));
+  if (c->cfg.scheme == 4 && c->batch) return fail(c, EP_ERR_ARG, "the fourth-order scheme runs single instances");
+  if (c->cfg.scheme == 4 && c->cfg.prec == 2)
+    return fail(c, EP_ERR_ARG, "the fourth-order scheme takes EP_PREC_F64 or EP_PREC_MIXED_F32");
   c->ws = reinterpret_cast<char*>(p);
   c->ws_bytes = bytes;
   if (c->batch) {
@@ -816,6 +909,8 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
     // cooperative residency: shrink G until it fits
     int bpc = 0;
     for (;;) {
+      if (c->cfg.scheme == 4 && sg)
+        return fail(c, EP_ERR_ARG, "the fourth-order scheme needs the Krylov slices in LDS (team too small)");
       EP_HIP(c, expv_max_blocks(c->cfg, c->one.model, chunk, sg, &bpc));
       if ((long long)bpc * c->cus >= G || G == 1) break;
       G = std::max(1, (int)((long long)bpc * c->cus));
@@ -857,6 +952,7 @@ ep_status ep_set_state(ep_ctx* c, double t, const double* u, const double* v) {
   I.hist_new = I.hist_old = -1;
   I.state_set = true;
   I.s0_pending = scaled_s0_mode(c);
+  I.m4_prev = false;
   return EP_OK;
 }
 
@@ -971,15 +1067,6 @@ ep_status ep_get_step_log(ep_ctx* c, int n, int32_t* m_corr, int32_t* m_pred, in
 }
 
 // --------------------------------------------------------------------------- stage calls
-static OpArgs op_from(const double* ulin, double tau, double t_eval) {
-  OpArgs op{};
-  op.tau = tau;
-  op.t_eval = t_eval;
-  op.nsets = ulin ? 1 : 0;
-  op.ulin[0] = ulin;
-  op.wts[0] = 1.0;
-  return op;
-}
 
 ep_status ep_apply_H(ep_ctx* c, const double* u_lin, const double* x, double* y) {
   ep_status s = need_bound(c);
@@ -1304,6 +1391,7 @@ ep_status ep_batch_set_state(ep_ctx* c, int32_t id, double t, const double* u, c
   EP_HIP(c, hipStreamSynchronize(c->stream));
   I.state_set = true;
   I.s0_pending = scaled_s0_mode(c);
+  I.m4_prev = false;
   return EP_OK;
 }
 

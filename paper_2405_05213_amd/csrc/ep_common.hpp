@@ -70,6 +70,10 @@ struct OpArgs {
   int nsets;                  // 0: H(0) (linear-elastic or rest state); 1 or 2 secant sets
   const double* ulin[2];      // physical nodal displacements of the secant sets
   double wts[2];              // weights of the sets (predictor: 1.75, -0.75)
+  // fourth-order scheme (kernels instantiated with SCH = 4): the operator is
+  // Omega = dt/2 (A_1 + A_2) - c4 [A_1, A_2], A_i with the set i and the load at t_eval
+  // (i = 1) or t_eval2 (i = 2); tau = 1
+  double dt4, c4, t_eval2;
 };
 
 struct KrylovCfg {
@@ -78,6 +82,8 @@ struct KrylovCfg {
   int prec;                   // 0 FP64, 1 FP32 element kernels, 2 stored BF16 element tangents
   int ortho;                  // 0: one team reduction per projection (sequential MGS);
                               // 1: MGS in compact-WY form, one vector reduction per step
+  int scheme;                 // time integrator: 2 (0 = 2) the paper's midpoint Magnus step with
+                              // predictor-corrector, 4 the two-term (fourth-order) Magnus step
 };
 
 // Per-projection-kind adaptive state (kept on device between launches).
@@ -117,6 +123,8 @@ struct KWork {
   double* X;                  // Lp: propagated vector
   double* F;                  // 24*n_elems element forces (slot-major)
   float* F32;
+  double* F2;                 // second slot array of the fourth-order scheme (u-part forces)
+  float* F2_32;
   unsigned long long* flags;  // G barrier generations
   unsigned long long* ring;   // 8 * G all-reduce slots
   unsigned long long* vring;  // 8 * G * vw vector all-reduce slots (compact-WY MGS)

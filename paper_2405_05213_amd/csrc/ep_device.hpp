@@ -677,6 +677,119 @@ __device__ __forceinline__ bool elem_force_qp(const Mesh& M, const OpArgs& op, i
   return ok;
 }
 
+// Contribution of one Gauss point's stress S to its element's 24 nodal forces, summed over
+// the element's 8 lanes by a reduce-scatter: lane q stores node q's force to its slot.
+template <typename T>
+__device__ __forceinline__ void qp_scatter_store(const Mesh& M, const QFactors<T>& Q, const T (&S)[3][3],
+                                                 const T* Jinv, T wdet, int q, int e, T* F) {
+  T St[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      St[i][j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
+  T f[8][3];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const T d0 = Q.dN(a, 0), d1 = Q.dN(a, 1), d2 = Q.dN(a, 2);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[a][i] = St[i][0] * d0 + St[i][1] * d1 + St[i][2] * d2;
+  }
+  const bool b4 = (q >> 2) & 1, b2 = (q >> 1) & 1, b1 = q & 1;
+  T k4[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T send = b4 ? f[a][i] : f[a + 4][i];
+      const T keep = b4 ? f[a + 4][i] : f[a][i];
+      k4[a][i] = keep + shfl_x(send, 4);
+    }
+  T k2[2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const T send = b2 ? k4[a][i] : k4[a + 2][i];
+      const T keep = b2 ? k4[a + 2][i] : k4[a][i];
+      k2[a][i] = keep + shfl_x(send, 2);
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T send = b1 ? k2[0][i] : k2[1][i];
+    const T keep = b1 ? k2[1][i] : k2[0][i];
+    F[((size_t)q * M.n_elems + e) * 3 + i] = keep + shfl_x(send, 1);
+  }
+}
+
+// Element forces of the fourth-order scheme's operator (one lane per Gauss point, 8 lanes
+// per element).  With X_u, X_v the gradients of M^{-1/2} x_u and M^{-1/2} x_v (times hinv),
+// h = dt/2 and c = sqrt(3) dt^2 / 12, and Phi_i the per-point H-matrix operator of set i:
+//   Fv <- Phi_1(h X_u - c X_v) + Phi_2(h X_u + c X_v)     (v-part of Omega x: -M^{-1/2} Fv)
+//   Fu <- Phi_1(c X_u) - Phi_2(c X_u)                      (u-part: -M^{-1/2} Fu)
+// since dt/2 (Hbar_1 + Hbar_2) x_u + c (Hbar_2 - Hbar_1) x_v and c (Hbar_1 - Hbar_2) x_u are
+// the H parts of Omega x.  Returns false if a set has J <= 0.
+template <typename T, int MODEL>
+__device__ __forceinline__ bool elem_force_qp_m4(const Mesh& M, const OpArgs& op, int e, const double* src,
+                                                 double hinv, T* Fv, T* Fu) {
+  const int q = threadIdx.x & 7;
+  const QFactors<T> Q(q);
+  int nd[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+  T Jinv[9], wdet;
+  const size_t gi = (M.congruent ? (size_t)q : (size_t)e * 8 + q) * 10;
+  if (sizeof(T) == 8) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo[gi + k]);
+    wdet = T(M.geo[gi + 9]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo32[gi + k]);
+    wdet = T(M.geo32[gi + 9]);
+  }
+  T Xu[3][3], Xv[3][3];
+  grad_gather(Q, nd, src, hinv, M.mih, Jinv, Xu);
+  grad_gather(Q, nd, src + M.n3, hinv, M.mih, Jinv, Xv);
+  const T h = T(0.5 * op.dt4), c = T(op.c4);
+  T Sv[3][3], Su[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Sv[i][k] = Su[i][k] = T(0);
+  bool ok = true;
+  double lam_d = 0.0, mu_d = 0.0;
+  if (MODEL == kSVK) rest_lame(kSVK, M.mp, lam_d, mu_d);
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const T sg = s == 0 ? T(-1) : T(1);    // -c X_v for set 1, +c X_v for set 2
+    T Ai[3][3], B[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        Ai[i][k] = h * Xu[i][k] + sg * c * Xv[i][k];
+        B[i][k] = c * Xu[i][k];
+      }
+    T Du[3][3];
+    grad_gather(Q, nd, op.ulin[s], 1.0, nullptr, Jinv, Du);
+    if constexpr (MODEL == kSVK) {
+      SecantSVK<T> sv;
+      svk_coeffs(Du, T(lam_d), T(mu_d), sv);
+      svk_apply(sv, T(lam_d), T(mu_d), T(1), Ai, Sv);
+      svk_apply(sv, T(lam_d), T(mu_d), -sg, B, Su);
+    } else {
+      Secant<T> sc;
+      ok &= secant_coeffs<T, MODEL>(Du, M.mp, sc);
+      secant_apply(sc, T(1), Ai, Sv);
+      secant_apply(sc, -sg, B, Su);
+    }
+  }
+  qp_scatter_store(M, Q, Sv, Jinv, wdet, q, e, Fv);
+  qp_scatter_store(M, Q, Su, Jinv, wdet, q, e, Fu);
+  return ok;
+}
+
 template <typename T>
 __device__ __forceinline__ void store_force(const Mesh& M, int e, const T (&f)[8][3], T* F) {
 #pragma unroll

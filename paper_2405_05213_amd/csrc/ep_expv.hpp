@@ -19,7 +19,8 @@ __host__ __device__ inline size_t expv_head_doubles(int ortho, int m_max) {
 
 // SG = 1: the workgroup's slices of w and of the newest basis vector live in device memory
 // (W.wscr, [w | v] rows of Lp doubles) and U holds only the expm scratch.
-template <typename T, int MODEL, int ORTHO, int SG>
+// SCH = 4: the operator of the fourth-order scheme (Omega of the two-term Magnus series).
+template <typename T, int MODEL, int ORTHO, int SG, int SCH = 2>
 __global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   extern __shared__ double lds[];
   const int C = A.W.chunk;
@@ -58,13 +59,19 @@ __global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   __syncthreads();
   GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false, 0u,
               A.W.vring, A.W.vw, 0u};
-  expv_body<T, MODEL, GridTeam, ORTHO>(tm, A, lw, lv, red, yb, flag, X);
+  expv_body<T, MODEL, GridTeam, ORTHO, SCH>(tm, A, lw, lv, red, yb, flag, X);
 }
 
 template <typename T, int MODEL, int SG>
 inline const void* expv_fn(int ortho) {
   return ortho == 1 ? reinterpret_cast<const void*>(&k_expv<T, MODEL, 1, SG>)
                     : reinterpret_cast<const void*>(&k_expv<T, MODEL, 0, SG>);
+}
+
+template <typename T, int MODEL>
+inline const void* expv_fn_m4(int ortho) {
+  return ortho == 1 ? reinterpret_cast<const void*>(&k_expv<T, MODEL, 1, 0, 4>)
+                    : reinterpret_cast<const void*>(&k_expv<T, MODEL, 0, 0, 4>);
 }
 
 template <int SG>

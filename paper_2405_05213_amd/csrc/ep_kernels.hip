@@ -412,12 +412,14 @@ size_t expv_lds_bytes(int chunk, int ortho, int m_max, int sg) {
   return head + u;
 }
 
-static const void* expv_kernel(int prec, int model, int ortho, int sg) {
+static const void* expv_kernel(int prec, int model, int ortho, int sg, int scheme) {
+  if (scheme == 4) return sg ? nullptr : expv_kernel_m4(prec, model, ortho);
   return sg ? expv_kernel_global(prec, model, ortho) : expv_kernel_sg<0>(prec, model, ortho);
 }
 
 hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int sg, int* blocks_per_cu) {
-  const void* fn = expv_kernel(cfg.prec, model, cfg.ortho, sg);
+  const void* fn = expv_kernel(cfg.prec, model, cfg.ortho, sg, cfg.scheme);
+  if (fn == nullptr) return hipErrorInvalidValue;
   const size_t lds = expv_lds_bytes(chunk, cfg.ortho, cfg.m_max, sg);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -437,7 +439,8 @@ hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
   const int nv = a.cfg.ortho == 1 ? kRing * a.W.G * a.W.vw : 0;
   const int n = nv > kRing * a.W.G ? nv : kRing * a.W.G;
   k_prep_team<<<(n + 255) / 256, 256, 0, st>>>(a.W.flags, a.W.ring, a.W.vring, a.W.G, nv);
-  const void* fn = expv_kernel(prec, a.M.model, a.cfg.ortho, a.W.slices_global);
+  const void* fn = expv_kernel(prec, a.M.model, a.cfg.ortho, a.W.slices_global, a.cfg.scheme);
+  if (fn == nullptr) return hipErrorInvalidValue;
   const size_t lds = expv_lds_bytes(a.W.chunk, a.cfg.ortho, a.cfg.m_max, a.W.slices_global);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -743,6 +746,47 @@ void launch_expm(int m, const double* H, double* E, double* scr, hipStream_t st)
     }
   }
   k_expm<<<1, kThreads, 0, st>>>(m, H, E, scr, 0);
+}
+
+// Displacements at the two Gauss nodes of a fourth-order step (u = M^{-1/2} ubar, v likewise):
+// cubic Hermite through (u, v) at t_prev (Sprev) and t (S), or on the first step the Taylor
+// polynomial u + s v + s^2/2 a with a = M^{-1} (scale(t) P_0 - R(u)), R = H(u) u.
+__global__ void k_m4_predict(int n3, const double* __restrict__ mih, const double* __restrict__ S,
+                             const double* __restrict__ Sprev, const double* __restrict__ R,
+                             const double* __restrict__ p0, double pscale_t, double t, double t_prev, double tau1,
+                             double tau2, int first, double* __restrict__ u1, double* __restrict__ u2) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n3) return;
+  const double m = mih[d];
+  const double u = m * S[d], v = m * S[n3 + d];
+  double r[2];
+  const double taus[2] = {tau1, tau2};
+  if (first) {
+    const double a = m * m * (pscale_t * p0[d] - R[d]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double s = taus[i] - t;
+      r[i] = u + s * v + 0.5 * s * s * a;
+    }
+  } else {
+    const double u0 = m * Sprev[d], v0 = m * Sprev[n3 + d];
+    const double h = t - t_prev;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double s = (taus[i] - t_prev) / h, s2 = s * s, s3 = s2 * s;
+      r[i] = (2 * s3 - 3 * s2 + 1) * u0 + (s3 - 2 * s2 + s) * h * v0 + (-2 * s3 + 3 * s2) * u + (s3 - s2) * h * v;
+    }
+  }
+  u1[d] = r[0];
+  u2[d] = r[1];
+}
+
+void launch_m4_predict(const Mesh& M, const double* S, const double* Sprev, const double* R, double pscale_t,
+                       double t, double t_prev, double tau1, double tau2, int first, double* u1, double* u2,
+                       hipStream_t st) {
+  if (M.n3 > 0)
+    k_m4_predict<<<nblk(M.n3, 256), 256, 0, st>>>(M.n3, M.mih, S, Sprev, R, M.p0, pscale_t, t, t_prev, tau1, tau2,
+                                                  first, u1, u2);
 }
 
 int energy_blocks(const Mesh& M) { return nblk(M.n_elems, 256); }

@@ -11,6 +11,7 @@ void launch_stiffness(const Mesh& M, double* Ke, hipStream_t st);
 void launch_stencil_blocks(const double* Ke, double* B, hipStream_t st);
 hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int sg, int* blocks_per_cu);
 const void* expv_kernel_global(int prec, int model, int ortho);
+const void* expv_kernel_m4(int prec, int model, int ortho);
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
 
 void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,
@@ -29,6 +30,9 @@ void launch_apply_H(const Mesh& M, const OpArgs& op, int prec, const double* x, 
 void launch_apply_A(const Mesh& M, const OpArgs& op, int prec, const double* x, double* y, double* F, float* F32,
                     int* err, hipStream_t st);
 void launch_expm(int m, const double* H, double* E, double* scr, hipStream_t st);
+void launch_m4_predict(const Mesh& M, const double* S, const double* Sprev, const double* R, double pscale_t,
+                       double t, double t_prev, double tau1, double tau2, int first, double* u1, double* u2,
+                       hipStream_t st);
 // stored BF16 element tangents (ep_tangent.hip)
 void launch_psi(const Mesh& M, uint16_t* psi, hipStream_t st);
 void launch_form_tangent(const Mesh& M, const OpArgs& op, const uint16_t* psi, uint16_t* kst, int* err,

@@ -115,6 +115,45 @@ __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, 
   return okA;
 }
 
+// Element forces of the fourth-order scheme's operator Omega (see elem_force_qp_m4): F gets
+// the v-part forces, F2 the u-part forces.  Linear elasticity: both sets are K, the u-part
+// vanishes and F = K M^{-1/2} x_u as in the second-order operator.
+template <typename T, int MODEL>
+__device__ __forceinline__ bool phase_elements_m4(const Mesh& M, const OpArgs& op, const double* src,
+                                                  double hinv, T* F, T* F2, int rank, int G, const T* ke) {
+  if constexpr (MODEL == kLinear) {
+    return phase_elements<T, MODEL>(M, op, src, hinv, F, rank, G, ke);
+  } else {
+    bool ok = true;
+    for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
+      ok &= elem_force_qp_m4<T, MODEL>(M, op, e, src, hinv, F, F2);
+    return ok;
+  }
+}
+
+// Entry g of f Omega v for the fourth-order scheme (src = v / hinv, xs = its augmented entry
+// / s0, ps1 / ps2 the load scales at the two Gauss nodes):
+//   u-part  dt x_v - M^{-1/2} Fu - c xs (p_2 - p_1)
+//   v-part  -M^{-1/2} Fv + dt/2 xs (p_1 + p_2)        (linear: -dt M^{-1/2} K M^{-1/2} x_u)
+template <typename T, int MODEL>
+__device__ __forceinline__ double m4_entry(const Mesh& M, const OpArgs& op, const T* F, const T* F2,
+                                           const double* src, double hinv, double xs, double ps1, double ps2,
+                                           double f, int g) {
+  const int n3 = M.n3;
+  if (g < n3) {
+    double w = op.dt4 * (src[n3 + g] * hinv) - op.c4 * xs * (ps2 - ps1) * M.p0bar[g];
+    if constexpr (MODEL != kLinear) w -= M.mih[g] * gather_force(M, F2, g / 3, g - (g / 3) * 3);
+    return f * w;
+  }
+  if (g < 2 * n3) {
+    const int d = g - n3;
+    const double s = gather_force(M, F, d / 3, d - (d / 3) * 3);
+    const double sc = MODEL == kLinear ? op.dt4 : 1.0;
+    return f * (-M.mih[d] * sc * s + 0.5 * op.dt4 * xs * (ps1 + ps2) * M.p0bar[d]);
+  }
+  return 0.0;
+}
+
 // Check point of step j (shared by both orthogonalisation forms): workgroup 0 exponentiates
 // H_j and decides; on convergence X <- V_j y with y = beta exp(H_j) e_1.  Returns 0 to go
 // on, 1 when the projection ends (R filled), -1 when the team died.
@@ -177,8 +216,9 @@ __device__ __forceinline__ int check_point(Team& tm, const ExpvArgs& A, int j, d
   return 0;
 }
 
-// X <- exp(f A) X on entry ||X|| = beta.  Every workgroup returns the same result.
-template <typename T, int MODEL, class Team>
+// X <- exp(f A) X on entry ||X|| = beta (SCH = 4: exp(f Omega) X).  Every workgroup returns
+// the same result.
+template <typename T, int MODEL, class Team, int SCH = 2>
 __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
                               double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
@@ -196,6 +236,8 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
   const int mcap = cfg.m_fixed > 0 ? cfg.m_fixed : cfg.m_max;
   const bool lead = tm.rank == 0;
   T* F = (sizeof(T) == 8) ? (T*)W.F : (T*)W.F32;
+  T* F2 = (sizeof(T) == 8) ? (T*)W.F2 : (T*)W.F2_32;
+  const double pscale2 = SCH == 4 ? load_scale(M, A.op.t_eval2) : 0.0;
 
   double hinv = 1.0 / beta;
   const double* src = W.X;
@@ -204,7 +246,9 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
   for (int j = 1; j <= mcap; ++j) {
     // ---- operator apply, part 1: element forces of the u-part of v_{j-1}
-    const bool okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
+    bool okA;
+    if constexpr (SCH == 4) okA = phase_elements_m4<T, MODEL>(M, A.op, src, hinv, F, F2, tm.rank, tm.G, (const T*)X.ke);
+    else okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;
     {
@@ -218,7 +262,9 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
       const int g = c0 + i;
       double w;
-      if (g < n3) {
+      if constexpr (SCH == 4) {
+        w = m4_entry<T, MODEL>(M, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
+      } else if (g < n3) {
         w = f * (src[n3 + g] * hinv);
       } else if (g < 2 * n3) {
         const int d = g - n3;
@@ -315,7 +361,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
 // Compact-WY form of the projection (see the file header).  Per step: the operator barrier,
 // one vector all-reduce of the 2j - 1 inner products, the fenced norm all-reduce.
-template <typename T, int MODEL, class Team>
+template <typename T, int MODEL, class Team, int SCH = 2>
 __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
                                   double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
@@ -334,6 +380,8 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
   const bool lead = tm.rank == 0;
   const int nw = (int)(blockDim.x >> 6), lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   T* F = (sizeof(T) == 8) ? (T*)W.F : (T*)W.F32;
+  T* F2 = (sizeof(T) == 8) ? (T*)W.F2 : (T*)W.F2_32;
+  const double pscale2 = SCH == 4 ? load_scale(M, A.op.t_eval2) : 0.0;
 
   double hinv = 1.0 / beta;
   const double* src = W.X;
@@ -345,7 +393,9 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
   double hmax = 0.0;
 
   for (int j = 1; j <= mcap; ++j) {
-    const bool okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
+    bool okA;
+    if constexpr (SCH == 4) okA = phase_elements_m4<T, MODEL>(M, A.op, src, hinv, F, F2, tm.rank, tm.G, (const T*)X.ke);
+    else okA = phase_elements<T, MODEL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;
     {
@@ -358,7 +408,9 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
       const int g = c0 + i;
       double w;
-      if (g < n3) {
+      if constexpr (SCH == 4) {
+        w = m4_entry<T, MODEL>(M, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
+      } else if (g < n3) {
         w = f * (src[n3 + g] * hinv);
       } else if (g < 2 * n3) {
         const int d = g - n3;
@@ -511,7 +563,7 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
 
 // wbar_out = exp(tau A) wbar_in with the sticky substep count and subspace-size hint of
 // this projection kind; writes statistics and sticky errors.
-template <typename T, int MODEL, class Team, int ORTHO = 0>
+template <typename T, int MODEL, class Team, int ORTHO = 0, int SCH = 2>
 __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, double* red, double* yb,
                           int* flag, const KLds& cx) {
   const Mesh& M = A.M;
@@ -541,9 +593,9 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
     for (int sub = 0; sub < k; ++sub) {
       ProjResult r;
       if constexpr (Team::kVecReduce && ORTHO == 1)
-        r = project_cwy<T, MODEL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+        r = project_cwy<T, MODEL, Team, SCH>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       else
-        r = project<T, MODEL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+        r = project<T, MODEL, Team, SCH>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       if (tm.dead) return;
       nmv += r.nmv;
       if (r.status != 0) { status = r.status; ok = false; break; }

@@ -45,6 +45,7 @@ _SIGS = {
     "ep_set_traction": [_vp, _i64, _vp, _vp, _i64, _vp, _vp],
     "ep_set_krylov": [_vp, _dbl, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, _dbl],
     "ep_set_precision": [_vp, C.c_int],
+    "ep_set_scheme": [_vp, C.c_int],
     "ep_set_orthogonalization": [_vp, C.c_int],
     "ep_get_launch": [_vp, _P(C.c_int), _P(C.c_int), _P(C.c_int), _P(C.c_int)],
     "ep_get_orthogonalization": [_vp, _P(C.c_int)],
@@ -182,6 +183,10 @@ class Context:
 
     def set_precision(self, prec: str):
         self._call("ep_set_precision", PRECISIONS[prec])
+
+    def set_scheme(self, order: int):
+        """Time integrator: 2 (the paper's second-order step) or 4 (two-term Magnus)."""
+        self._call("ep_set_scheme", int(order))
 
     def set_orthogonalization(self, mode: int):
         """-1 automatic, 0 sequential MGS, 1 MGS in compact-WY form (see include/ep.h)."""
@@ -371,7 +376,7 @@ def batch_from_problems(probs, device=0, tol=None, m_max=32, check_every=4, m_fi
 
 
 def solver_from_problem(prob, device=0, tol=None, m_max=64, check_every=4, m_fixed=0, k_fixed=0,
-                        max_substeps=64, s0=-1.0, precision="f64", workgroups=0, stream=None, ortho=-1):
+                        max_substeps=64, s0=-1.0, precision="f64", workgroups=0, stream=None, ortho=-1, scheme=2):
     """Context set up from a workloads.Problem, bound and at the problem's initial state."""
     ctx = Context(device, stream=stream)
     ctx.set_mesh(prob.xyz, prob.conn)
@@ -382,6 +387,7 @@ def solver_from_problem(prob, device=0, tol=None, m_max=64, check_every=4, m_fix
         ctx.set_traction(prob.faces, prob.t0, prob.knots_t, prob.knots_s)
     ctx.set_krylov(prob.tol if tol is None else tol, m_max, check_every, m_fixed, k_fixed, max_substeps, s0)
     ctx.set_precision(precision)
+    ctx.set_scheme(scheme)
     ctx.set_launch(workgroups)
     ctx.set_orthogonalization(ortho)
     ctx.bind()

@@ -145,3 +145,14 @@ def test_precision_modes():
     assert L.ep_set_precision(b.h, 2) == epmod.EP_ERR_ARG
     assert L.ep_set_precision(b.h, 1) == epmod.EP_OK
     assert b.workspace_size() > 0
+
+
+def test_scheme_arguments():
+    """ep_set_scheme takes 2 or 4, before binding."""
+    c = _host_ctx()
+    for order in (0, 1, 3, 6):
+        with pytest.raises(epmod.EPError) as e:
+            c.set_scheme(order)
+        assert e.value.code == epmod.EP_ERR_ARG
+    c.set_scheme(4)
+    c.set_scheme(2)
