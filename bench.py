@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--matvec-only", action="store_true",
                     help="only the stand-alone FP64 operator applies on the 64^3 and 128^3 cubes (profiling)")
+    ap.add_argument("--schemes-only", action="store_true",
+                    help="only the second- vs fourth-order comparison on the Neo-Hookean cantilever")
     ap.add_argument("--tangents-only", action="store_true",
                     help="only the BF16 tangent formation / apply on the 64^3 Yeoh block (profiling)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -431,7 +433,7 @@ def main():
     probs = batch_instances(args.instances, seed=5, dt=args.batch_dt)
     # the oracle on the host cores first: its worker processes are forked before the GPU is touched
     cpu = None
-    if not (args.no_cpu or args.matvec_only or args.tangents_only):
+    if not (args.no_cpu or args.matvec_only or args.tangents_only or args.schemes_only):
         cpu = cpu_baseline_batch(probs, args.cpu_seconds, args)
     import torch
 
@@ -443,6 +445,9 @@ def main():
         copy_probe(torch)
     if args.matvec_only:
         print(json.dumps(run_matvecs(config, stream, torch, args)))
+        return
+    if args.schemes_only:
+        print(json.dumps({"c3_second_vs_fourth_order": run_scheme_comparison(config, stream, torch, args)}))
         return
     if args.tangents_only:
         cube = config("c4")
@@ -555,11 +560,49 @@ def run_extras(config, stream, torch, args):
                     "energy": abs((en[0] + en[1] - en[2]) - (er[0] + er[1] - er[2])) / (er[0] + er[1])}
             r["ctx"].close()
             extra[f"{name}_{prec}"] = e
+    extra["c3_second_vs_fourth_order"] = run_scheme_comparison(config, stream, torch, args)
     extra.update(run_matvecs(config, stream, torch, args))
     cube = config("c4")
     u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
     extra["tangents_cube64_yeoh_bf16"] = run_tangents(cube, u_aff, 20, stream, torch, args)
     return extra
+
+
+def run_scheme_comparison(config, stream, torch, args):
+    """Second- against fourth-order Magnus step on the 160x16x16 Neo-Hookean cantilever (FP64):
+    from rest over the first 5 ms of the load ramp, the element-wise error of u and v against a
+    fourth-order run at dt = T/320, and the GPU time of each run (HIP events)."""
+    from paper_2405_05213_amd import solver_from_problem
+    T = 0.005
+    p0 = config("c3")
+
+    def run(scheme, n):
+        p = config("c3", dt=T / n)
+        ctx = solver_from_problem(p, m_max=64, scheme=scheme, stream=stream.cuda_stream)
+        ctx.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.step(p.dt, n)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        _, u, v = ctx.get_state()
+        ms = e0.elapsed_time(e1)
+        st = ctx.stats()
+        ctx.close()
+        return u, v, ms, st
+
+    ur, vr, ms_ref, _ = run(4, 320)
+    out = {"workload": f"c3 {p0.grid}, first {T * 1e3:g} ms of the load ramp, FP64, tol 1e-10",
+           "reference": f"fourth-order scheme at dt = {T / 320:g} s ({ms_ref:.0f} ms)", "runs": []}
+    for scheme in (2, 4):
+        for n in (10, 20, 40):
+            u, v, ms, st = run(scheme, n)
+            eu = float(np.abs(u - ur).max() / np.abs(ur).max())
+            ev = float(np.abs(v - vr).max() / np.abs(vr).max())
+            out["runs"].append({"scheme": scheme, "dt": T / n, "steps": n, "gpu_ms": ms, "ms_per_step": ms / n,
+                                "matvecs": st["matvecs"], "err_u": eu, "err_v": ev})
+            log(args, f"  scheme {scheme} dt={T / n:g}: {ms / n:.3f} ms/step, err u {eu:.2e} v {ev:.2e}")
+    return out
 
 
 def run_matvecs(config, stream, torch, args):
