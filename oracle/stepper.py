@@ -34,7 +34,7 @@ class Propagator:
                  m_fixed: int = 0, k_fixed: int = 0, max_substeps: int = 64, s0: float | None = None):
         self.prob = prob
         self.mat = Material(prob.model, prob.params)
-        self.fem = Discretization(prob.xyz, prob.conn, self.mat, prob.rho)
+        self.fem = Discretization(prob.xyz, prob.conn, self.mat, prob.rho, elem=getattr(prob, "elem", "hex8"))
         n3 = 3 * prob.n_nodes
         self.n3 = n3
         self.free = np.setdiff1d(np.arange(n3), np.asarray(prob.clamped, dtype=np.int64))

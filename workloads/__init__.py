@@ -19,6 +19,11 @@ Conventions
 * DOF id = 3 * node + component; all nodal vectors are node-major (x, y, z).
 * a quad face lists its 4 nodes counter-clockwise seen from outside, so the
   right-hand rule gives the outward normal.
+* hex27 (quadratic, Q2) elements: local node a = i + 3 j + 9 k, (i, j, k) in {0,1,2}^3 at
+  local coordinates (i-1, j-1, k-1); a box of nx x ny x nz Q2 elements has the node
+  lattice of the 2nx x 2ny x 2nz hex8 box.  A loaded Q2 face lists its 9 nodes p + 3 q,
+  (p, q) in {0,1,2}^2 along its two in-plane axes, ordered so that the derivatives of the
+  face map along p then q give the outward normal.
 * material models and their parameter tuples:
     'linear' : (E [Pa], nu)
     'nh'     : (mu [Pa], lambda [Pa])            compressible Neo-Hookean
@@ -34,7 +39,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "box_mesh", "box_face_quads", "box_face_nodes", "config",
-    "batch_instances", "distort", "MODELS",
+    "batch_instances", "distort", "MODELS", "q2_of", "box_mesh_q2", "box_face_quads_q2",
 ]
 
 MODELS = {"linear": 0, "nh": 1, "yeoh": 2}
@@ -62,6 +67,7 @@ class Problem:
     tol: float = 1e-10         # Krylov tolerance (relative to the propagated norm)
     grid: Optional[tuple] = None   # (nx, ny, nz) when the mesh is a lattice box
     extra: dict = field(default_factory=dict)
+    elem: str = "hex8"         # 'hex8' (trilinear) or 'hex27' (quadratic Lagrange, Q2)
 
     @property
     def n_nodes(self) -> int:
@@ -133,6 +139,73 @@ def box_face_quads(nx: int, ny: int, nz: int, axis: int, side: int) -> np.ndarra
             outward_is_ab = (axis != 1) == (side == 1)
             quads.append(corners if outward_is_ab else corners[::-1])
     return np.asarray(quads, dtype=np.int32)
+
+
+def box_mesh_q2(nx: int, ny: int, nz: int, lx: float, ly: float, lz: float):
+    """Lattice box split into nx*ny*nz quadratic (27-node) hexahedra; the nodes are the
+    lattice of the 2nx x 2ny x 2nz hex8 box, node (I, J, K) = I + (2nx+1)(J + (2ny+1)K)."""
+    xyz, _ = box_mesh(2 * nx, 2 * ny, 2 * nz, lx, ly, lz)
+    NX, NY = 2 * nx + 1, 2 * ny + 1
+    ez, ey, ex = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    cols = []
+    for k in range(3):
+        for j in range(3):
+            for i in range(3):
+                cols.append((2 * ex + i) + NX * ((2 * ey + j) + NY * (2 * ez + k)))
+    return xyz, np.stack(cols, axis=1).astype(np.int32)
+
+
+def box_face_quads_q2(nx: int, ny: int, nz: int, axis: int, side: int) -> np.ndarray:
+    """9-node faces of a Q2 box's boundary face axis / side (outward orientation)."""
+    NX, NY = 2 * nx + 1, 2 * ny + 1
+
+    def nid(I, J, K):
+        return I + NX * (J + NY * K)
+
+    dims = (nx, ny, nz)
+    a, b = [d for d in range(3) if d != axis]
+    fixed = 0 if side == 0 else 2 * dims[axis]
+    outward_is_ab = (axis != 1) == (side == 1)
+    faces = []
+    for q in range(dims[b]):
+        for p in range(dims[a]):
+            nodes = []
+            for qq in range(3):
+                for pp in range(3):
+                    ijk = [0, 0, 0]
+                    ijk[axis] = fixed
+                    # swapping the in-plane roles flips the face's orientation
+                    if outward_is_ab:
+                        ijk[a], ijk[b] = 2 * p + pp, 2 * q + qq
+                    else:
+                        ijk[a], ijk[b] = 2 * p + qq, 2 * q + pp
+                    nodes.append(nid(*ijk))
+            faces.append(nodes)
+    return np.asarray(faces, dtype=np.int32)
+
+
+def q2_of(prob: Problem) -> Problem:
+    """The same box, loads, supports and initial fields on quadratic (Q2) elements: a lattice
+    box of nx x ny x nz hex8 cells (nx, ny, nz even) has the nodes of the nx/2 x ny/2 x nz/2
+    Q2 box, so nodal data carry over; the loaded faces become 9-node faces."""
+    nx, ny, nz = prob.grid
+    if nx % 2 or ny % 2 or nz % 2:
+        raise ValueError("Q2 box needs even hex8 cell counts")
+    lx, ly, lz = (prob.xyz.max(axis=0) - prob.xyz.min(axis=0))
+    xyz, conn = box_mesh_q2(nx // 2, ny // 2, nz // 2, lx, ly, lz)
+    xyz = xyz + prob.xyz.min(axis=0)
+    assert np.allclose(xyz, prob.xyz)
+    # loaded faces: find which box face the hex8 quads lie on
+    faces = np.zeros((0, 9), np.int32)
+    if len(prob.faces):
+        c = prob.xyz[np.asarray(prob.faces)].reshape(-1, 3)
+        span = c.max(axis=0) - c.min(axis=0)
+        axis = int(np.argmin(span))
+        side = int(abs(c[0, axis] - prob.xyz[:, axis].max()) < 1e-12 * max(1.0, abs(c[0, axis])))
+        faces = box_face_quads_q2(nx // 2, ny // 2, nz // 2, axis, side)
+    return replace(prob, name=prob.name + "-q2", conn=conn, faces=faces, elem="hex27",
+                   grid=(nx // 2, ny // 2, nz // 2))
 
 
 def _dofs_of_nodes(nodes: np.ndarray, comps=(0, 1, 2)) -> np.ndarray:
