@@ -107,6 +107,16 @@ ep_status ep_set_stream(ep_ctx* ctx, void* hip_stream);
 ep_status ep_set_mesh_hex8(ep_ctx* ctx, int64_t n_nodes, const double* xyz_host,
                            int64_t n_elems, const int32_t* conn_host);
 
+/* Mesh of quadratic 27-node hexahedra, the paper's element (Sec. 2.2: quadratic Lagrange
+ * interpolation; 3x3x3 Gauss for the internal force, the 3-point Gauss-Lobatto rule at the
+ * nodes for a diagonal mass).  conn_host[27*n_elems]: local node a = i + 3 j + 9 k at the
+ * local point (i-1, j-1, k-1).  Loaded faces (ep_set_traction) then list 9 nodes each,
+ * p + 3 q at (p-1, q-1) with the outward normal along d/dp x d/dq; 3x3 Gauss.  Single-instance
+ * contexts, EP_PREC_F64 or EP_PREC_MIXED_F32, second-order scheme (EP_ERR_ARG otherwise, at
+ * ep_bind_workspace). */
+ep_status ep_set_mesh_hex27(ep_ctx* ctx, int64_t n_nodes, const double* xyz_host,
+                            int64_t n_elems, const int32_t* conn_host);
+
 /* Material (see ep_model) and reference density rho (kg/m^3). */
 ep_status ep_set_material(ep_ctx* ctx, ep_model model, const double* params_host,
                           int n_params, double rho);
@@ -115,7 +125,8 @@ ep_status ep_set_material(ep_ctx* ctx, ep_model model, const double* params_host
  * are allowed.  The clamped DOFs are eliminated from the system (held at zero). */
 ep_status ep_set_dirichlet(ep_ctx* ctx, int64_t n_dofs, const int32_t* dof_ids_host);
 
-/* Dead traction t(t) = scale(t) * t0 on quad faces face_nodes_host[4*n_faces]
+/* Dead traction t(t) = scale(t) * t0 on quad faces face_nodes_host[4*n_faces] (9 per face
+ * on a mesh of quadratic hexahedra)
  * (weak-form term 3, Sec. 2.2).  scale(t) is piecewise linear through the n_knots
  * pairs (t_knots, scale), held constant before the first and after the last knot;
  * t_knots must be ascending.  n_faces = 0 means no load. */

@@ -37,6 +37,8 @@ struct Layout {
 struct Inst {
   // inputs
   int64_t n_nodes = 0, n_elems = 0;
+  int npe = 8;                  // nodes per element: 8 (hex8) or 27 (quadratic hexahedron)
+  int nfn = 4;                  // nodes per loaded face: 4 or 9
   std::vector<double> xyz;
   std::vector<int32_t> conn;
   int model = -1;
@@ -118,13 +120,14 @@ static ep_status fail(ep_ctx* c, ep_status s, const std::string& msg) {
 static bool is_gpu(const ep_ctx* c) { return c->device >= 0; }
 
 // ------------------------------------------------------------------------------ validation
-static ep_status check_mesh(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn) {
+static ep_status check_mesh(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
+                            int npe = 8) {
   if (n_nodes <= 0 || n_elems <= 0) return fail(c, EP_ERR_ARG, "mesh needs n_nodes > 0 and n_elems > 0");
   if (!xyz || !conn) return fail(c, EP_ERR_ARG, "null mesh array");
   if (n_nodes > (1LL << 28) || n_elems > (1LL << 27)) return fail(c, EP_ERR_ARG, "mesh too large for 32-bit indexing");
   for (int64_t i = 0; i < 3 * n_nodes; ++i)
     if (!std::isfinite(xyz[i])) return fail(c, EP_ERR_ARG, "non-finite node coordinate");
-  for (int64_t i = 0; i < 8 * n_elems; ++i)
+  for (int64_t i = 0; i < npe * n_elems; ++i)
     if (conn[i] < 0 || conn[i] >= n_nodes) return fail(c, EP_ERR_ARG, "connectivity entry out of range");
   return EP_OK;
 }
@@ -153,10 +156,10 @@ static ep_status check_material(ep_ctx* c, int model, const double* p, int n, do
 }
 
 static ep_status check_traction(ep_ctx* c, int64_t n_nodes, int64_t n_faces, const int32_t* fn, const double* t0,
-                                int64_t n_knots, const double* kt, const double* ks) {
+                                int64_t n_knots, const double* kt, const double* ks, int nfn = 4) {
   if (n_faces < 0 || n_knots < 0) return fail(c, EP_ERR_ARG, "negative count");
   if (n_faces > 0 && (!fn || !t0)) return fail(c, EP_ERR_ARG, "null face array or traction");
-  for (int64_t i = 0; i < 4 * n_faces; ++i)
+  for (int64_t i = 0; i < nfn * n_faces; ++i)
     if (fn[i] < 0 || fn[i] >= n_nodes) return fail(c, EP_ERR_ARG, "face node out of range");
   if (n_faces > 0)
     for (int i = 0; i < 3; ++i)
@@ -170,11 +173,14 @@ static ep_status check_traction(ep_ctx* c, int64_t n_nodes, int64_t n_faces, con
   return EP_OK;
 }
 
-static void fill_mesh(Inst& I, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn) {
+static void fill_mesh(Inst& I, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn,
+                      int npe = 8) {
   I.n_nodes = n_nodes;
   I.n_elems = n_elems;
+  I.npe = npe;
+  I.nfn = npe == 27 ? 9 : 4;
   I.xyz.assign(xyz, xyz + 3 * n_nodes);
-  I.conn.assign(conn, conn + 8 * n_elems);
+  I.conn.assign(conn, conn + (size_t)npe * n_elems);
   I.n3 = (int)(3 * n_nodes);
   I.L = 2 * I.n3 + 1;
   I.Lp = (I.L + 63) / 64 * 64;
@@ -182,7 +188,7 @@ static void fill_mesh(Inst& I, int64_t n_nodes, const double* xyz, int64_t n_ele
 
 static void fill_traction(Inst& I, int64_t n_faces, const int32_t* fn, const double* t0, int64_t n_knots,
                           const double* kt, const double* ks) {
-  I.faces.assign(fn ? fn : (const int32_t*)nullptr, fn ? fn + 4 * n_faces : (const int32_t*)nullptr);
+  I.faces.assign(fn ? fn : (const int32_t*)nullptr, fn ? fn + (size_t)I.nfn * n_faces : (const int32_t*)nullptr);
   for (int i = 0; i < 3; ++i) I.t0[i] = (n_faces > 0 && t0) ? t0[i] : 0.0;
   I.n_knots = (int)n_knots;
   I.knots.assign(2 * n_knots, 0.0);
@@ -231,31 +237,32 @@ static int pick_G(const ep_ctx* c, const Inst& I, int* chunk, int* sg) {
 }
 
 static void plan_inst(const ep_ctx* c, Inst& I, Layout& L, int Gmax) {
-  const size_t n3 = I.n3, ne = I.n_elems, nn = I.n_nodes, nf = I.faces.size() / 4;
+  const size_t n3 = I.n3, ne = I.n_elems, nn = I.n_nodes, nf = I.faces.size() / I.nfn;
+  const size_t npe = I.npe, nfn = I.nfn;
   const size_t Lp = I.Lp, mm = c->cfg.m_max;
   I.o_xyz = L.take(8 * 3 * nn);
-  I.o_conn = L.take(4 * 8 * ne);
+  I.o_conn = L.take(4 * npe * ne);
   I.o_incp = L.take(4 * (nn + 1));
-  I.o_inc = L.take(4 * 8 * ne);
-  I.o_geo = L.take(8 * 80 * ne);
-  I.o_geo32 = L.take(4 * 80 * ne);
-  I.o_vdet = L.take(8 * 8 * ne);
+  I.o_inc = L.take(4 * npe * ne);
+  I.o_geo = L.take(8 * 10 * npe * ne);      // J^{-1}, w det J at the npe Gauss points
+  I.o_geo32 = L.take(4 * 10 * npe * ne);
+  I.o_vdet = L.take(8 * npe * ne);
   I.o_mih = L.take(8 * n3);
   I.o_mh = L.take(8 * n3);
   I.o_p0 = L.take(8 * n3);
   I.o_p0bar = L.take(8 * n3);
-  I.o_faces = L.take(4 * 4 * std::max<size_t>(nf, 1));
+  I.o_faces = L.take(4 * nfn * std::max<size_t>(nf, 1));
   I.o_fincp = L.take(4 * (nn + 1));
-  I.o_finc = L.take(4 * 4 * std::max<size_t>(nf, 1));
-  I.o_ff = L.take(8 * 12 * std::max<size_t>(nf, 1));
+  I.o_finc = L.take(4 * nfn * std::max<size_t>(nf, 1));
+  I.o_ff = L.take(8 * 3 * nfn * std::max<size_t>(nf, 1));
   I.o_knots = L.take(8 * std::max<size_t>(I.knots.size(), 2));
   I.o_clamp = L.take(n3);
   I.o_S = L.take(8 * Lp);
   I.o_X = L.take(8 * Lp);
   I.o_Wun = L.take(8 * Lp);
   I.o_V = L.take(8 * Lp * (mm + 1));
-  I.o_F = L.take(8 * 24 * ne);
-  I.o_F32 = L.take(4 * 24 * ne);
+  I.o_F = L.take(8 * 3 * npe * ne);
+  I.o_F32 = L.take(4 * 3 * npe * ne);
   I.o_hist = L.take(8 * 3 * n3);
   I.o_stage = L.take(8 * 2 * n3);
   // G barrier flags + 8 G ring slots (+ 8 G vector slots of 2 m_max values)
@@ -299,23 +306,25 @@ static size_t plan_all(ep_ctx* c) {
 // incidence lists (integer bookkeeping)
 static void build_incidence(Inst& I) {
   const int64_t nn = I.n_nodes, ne = I.n_elems;
+  const int npe = I.npe;
   I.inc_ptr.assign(nn + 1, 0);
   for (int64_t e = 0; e < ne; ++e)
-    for (int a = 0; a < 8; ++a) I.inc_ptr[I.conn[e * 8 + a] + 1]++;
+    for (int a = 0; a < npe; ++a) I.inc_ptr[I.conn[e * npe + a] + 1]++;
   for (int64_t n = 0; n < nn; ++n) I.inc_ptr[n + 1] += I.inc_ptr[n];
-  I.inc.assign(8 * ne, 0);
+  I.inc.assign(npe * ne, 0);
   std::vector<int32_t> pos(I.inc_ptr.begin(), I.inc_ptr.end() - 1);
-  for (int a = 0; a < 8; ++a)          // slot-major order: a outer, e inner
-    for (int64_t e = 0; e < ne; ++e) I.inc[pos[I.conn[e * 8 + a]]++] = (int32_t)(a * ne + e);
-  const int64_t nf = I.faces.size() / 4;
+  for (int a = 0; a < npe; ++a)        // slot-major order: a outer, e inner
+    for (int64_t e = 0; e < ne; ++e) I.inc[pos[I.conn[e * npe + a]]++] = (int32_t)(a * ne + e);
+  const int nfn = I.nfn;
+  const int64_t nf = I.faces.size() / nfn;
   I.finc_ptr.assign(nn + 1, 0);
   for (int64_t f = 0; f < nf; ++f)
-    for (int b = 0; b < 4; ++b) I.finc_ptr[I.faces[f * 4 + b] + 1]++;
+    for (int b = 0; b < nfn; ++b) I.finc_ptr[I.faces[f * nfn + b] + 1]++;
   for (int64_t n = 0; n < nn; ++n) I.finc_ptr[n + 1] += I.finc_ptr[n];
-  I.finc.assign(std::max<int64_t>(4 * nf, 1), 0);
+  I.finc.assign(std::max<int64_t>(nfn * nf, 1), 0);
   std::vector<int32_t> fp(I.finc_ptr.begin(), I.finc_ptr.end() - 1);
   for (int64_t f = 0; f < nf; ++f)
-    for (int b = 0; b < 4; ++b) I.finc[fp[I.faces[f * 4 + b]]++] = (int32_t)(f * 4 + b);
+    for (int b = 0; b < nfn; ++b) I.finc[fp[I.faces[f * nfn + b]]++] = (int32_t)(f * nfn + b);
   I.clamp_mask.assign(I.n3, 0);
   for (int32_t d : I.clamped) I.clamp_mask[d] = 1;
 }
@@ -363,7 +372,7 @@ static ep_status resolve_s0(ep_ctx* c, Inst& I, double dt) {
 // A structured box: node (i, j, k) = i + (nx+1)(j + (ny+1)k), elements in i-fastest order
 // with VTK corner order.  Read off element 0 and verified on every element.
 static bool lattice_dims(const Inst& I, int lat[3]) {
-  if (I.n_elems < 1) return false;
+  if (I.n_elems < 1 || I.npe != 8) return false;
   const int32_t* c0 = I.conn.data();
   const int64_t sx = c0[3] - c0[0], sxy = c0[4] - c0[0];
   if (c0[0] != 0 || c0[1] != 1 || sx < 2 || sxy % sx != 0) return false;
@@ -408,7 +417,7 @@ static double congruence_tol(const Inst& I) {
 static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   hipStream_t st = c->stream;
   build_incidence(I);
-  const size_t nf = I.faces.size() / 4;
+  const size_t nf = I.faces.size() / I.nfn;
   EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_xyz), I.xyz.data(), 8 * I.xyz.size(), hipMemcpyHostToDevice, st));
   EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_conn), I.conn.data(), 4 * I.conn.size(), hipMemcpyHostToDevice, st));
   EP_HIP(c, hipMemcpyAsync(dptr<char>(c, I.o_incp), I.inc_ptr.data(), 4 * I.inc_ptr.size(), hipMemcpyHostToDevice, st));
@@ -428,14 +437,14 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_log), 0, sizeof(StepLog), st));
   EP_HIP(c, hipMemsetAsync(dptr<char>(c, I.o_H), 0, 8 * (size_t)(c->cfg.m_max + 1) * c->cfg.m_max, st));
   int* flags = dptr<int>(c, I.o_flags);
-  launch_geometry(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_conn), (int)I.n_elems, dptr<double>(c, I.o_geo),
+  launch_geometry(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_conn), (int)I.n_elems, I.npe, dptr<double>(c, I.o_geo),
                   dptr<float>(c, I.o_geo32), dptr<double>(c, I.o_vdet), flags + 0, st);
-  launch_congruence(dptr<double>(c, I.o_geo), (int)I.n_elems, congruence_tol(I), flags + 1, st);
+  launch_congruence(dptr<double>(c, I.o_geo), (int)I.n_elems, I.npe, congruence_tol(I), flags + 1, st);
   EP_HIP(c, hipGetLastError());
-  launch_mass((int)I.n_nodes, (int)I.n_elems, dptr<int>(c, I.o_incp), dptr<int>(c, I.o_inc),
+  launch_mass((int)I.n_nodes, (int)I.n_elems, I.npe, dptr<int>(c, I.o_incp), dptr<int>(c, I.o_inc),
               dptr<double>(c, I.o_vdet), I.rho, dptr<unsigned char>(c, I.o_clamp), dptr<double>(c, I.o_mih),
               dptr<double>(c, I.o_mh), st);
-  launch_faces(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_faces), (int)nf, I.t0, dptr<double>(c, I.o_ff),
+  launch_faces(dptr<double>(c, I.o_xyz), dptr<int>(c, I.o_faces), (int)nf, I.nfn, I.t0, dptr<double>(c, I.o_ff),
                (int)I.n_nodes, dptr<int>(c, I.o_fincp), dptr<int>(c, I.o_finc), dptr<double>(c, I.o_mih),
                dptr<double>(c, I.o_p0), dptr<double>(c, I.o_p0bar), st);
   EP_HIP(c, hipGetLastError());
@@ -446,6 +455,7 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   Mesh& M = I.M;
   M.n_nodes = (int)I.n_nodes;
   M.n_elems = (int)I.n_elems;
+  M.npe = I.npe;
   M.n3 = I.n3;
   M.L = I.L;
   M.Lp = I.Lp;
@@ -468,7 +478,7 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   M.ke = nullptr;
   M.lat[0] = M.lat[1] = M.lat[2] = 0;
   M.stencil = nullptr;
-  if (M.congruent && I.n_elems > 0) {
+  if (M.congruent && I.n_elems > 0 && I.npe == 8) {
     launch_stiffness(M, dptr<double>(c, I.o_ke), st);
     EP_HIP(c, hipGetLastError());
     M.ke = dptr<double>(c, I.o_ke);
@@ -770,6 +780,21 @@ ep_status ep_set_mesh_hex8(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_
   return EP_OK;
 }
 
+ep_status ep_set_mesh_hex27(ep_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_elems, const int32_t* conn) {
+  if (!c) return EP_ERR_ARG;
+  if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
+  if (c->batch) return fail(c, EP_ERR_ARG, "batches take hex8 meshes");
+  ep_status s = check_mesh(c, n_nodes, xyz, n_elems, conn, 27);
+  if (s != EP_OK) return s;
+  fill_mesh(c->one, n_nodes, xyz, n_elems, conn, 27);
+  c->one.clamped.clear();
+  c->one.faces.clear();
+  c->one.n_knots = 0;
+  c->one.knots.clear();
+  c->mesh_set = true;
+  return EP_OK;
+}
+
 ep_status ep_set_material(ep_ctx* c, ep_model model, const double* p, int n, double rho) {
   if (!c) return EP_ERR_ARG;
   if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
@@ -798,7 +823,7 @@ ep_status ep_set_traction(ep_ctx* c, int64_t n_faces, const int32_t* fn, const d
   if (!c) return EP_ERR_ARG;
   if (c->bound) return fail(c, EP_ERR_ORDER, "setup after ep_bind_workspace");
   if (!c->mesh_set) return fail(c, EP_ERR_ORDER, "ep_set_traction before ep_set_mesh_hex8");
-  ep_status s = check_traction(c, c->one.n_nodes, n_faces, fn, t0, n_knots, kt, ks);
+  ep_status s = check_traction(c, c->one.n_nodes, n_faces, fn, t0, n_knots, kt, ks, c->one.nfn);
   if (s != EP_OK) return s;
   fill_traction(c->one, n_faces, fn, t0, n_knots, kt, ks);
   return EP_OK;
@@ -896,6 +921,8 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
   if (!is_gpu(c)) return fail(c, EP_ERR_HIP, "host-only context cannot bind device memory");
   EP_HIP(c, hipSetDevice(c->device));
   if (c->cfg.scheme == 4 && c->batch) return fail(c, EP_ERR_ARG, "the fourth-order scheme runs single instances");
+  if (!c->batch && c->one.npe == 27 && (c->cfg.prec == 2 || c->cfg.scheme == 4))
+    return fail(c, EP_ERR_ARG, "quadratic elements take EP_PREC_F64 / EP_PREC_MIXED_F32 and the second-order scheme");
   if (c->cfg.scheme == 4 && c->cfg.prec == 2)
     return fail(c, EP_ERR_ARG, "the fourth-order scheme takes EP_PREC_F64 or EP_PREC_MIXED_F32");
   c->ws = reinterpret_cast<char*>(p);

@@ -37,6 +37,7 @@ constexpr int kErrKrylov = -4, kErrInverted = -5, kErrNonfinite = -6, kErrDevice
 // vector layout is [ubar (n3) | vbar (n3) | s | zero padding up to Lp].
 struct Mesh {
   int n_nodes, n_elems, n3;
+  int npe;                    // nodes (and Gauss points) per element: 8 (hex8) or 27 (Q2)
   int L, Lp;                  // L = 2*n3 + 1, Lp = padded row stride of V
   const int* conn;            // [n_elems*8]
   const int* inc_ptr;         // [n_nodes+1] node -> element-slot CSR

@@ -79,16 +79,76 @@ __global__ void k_geometry(const double* __restrict__ xyz, const int* __restrict
   if (!ok) atomicOr(bad, 1);
 }
 
+// Q2 geometry (one thread per element): J^{-1} and w det J at the 27 Gauss points, and at
+// each node w_a det J(xi_a) with w_a the product of the 3-point Gauss-Lobatto weights
+// (1/3, 4/3, 1/3), the node's share of the element's lumped mass per unit density.
+__global__ void k_geometry27(const double* __restrict__ xyz, const int* __restrict__ conn, int n_e,
+                             double* __restrict__ geo, float* __restrict__ geo32, double* __restrict__ vdet,
+                             int* __restrict__ bad) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_e) return;
+  bool ok = true;
+  for (int pt = 0; pt < 2 * kQ2Nodes; ++pt) {
+    const bool gauss = pt < kQ2Nodes;
+    const int q = gauss ? pt : pt - kQ2Nodes;
+    const int qi = q % 3, qj = (q / 3) % 3, qk = q / 9;
+    const double x = gauss ? q2_gpt(qi) : double(qi - 1);
+    const double y = gauss ? q2_gpt(qj) : double(qj - 1);
+    const double z = gauss ? q2_gpt(qk) : double(qk - 1);
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int a = 0; a < kQ2Nodes; ++a) {
+      const int i = a % 3, j = (a / 3) % 3, k = a / 9;
+      const double li = lag3(i, x), lj = lag3(j, y), lk = lag3(k, z);
+      const double d[3] = {dlag3(i, x) * lj * lk, li * dlag3(j, y) * lk, li * lj * dlag3(k, z)};
+      const int n = conn[(size_t)e * kQ2Nodes + a];
+      for (int r = 0; r < 3; ++r) {
+        const double X = xyz[(size_t)n * 3 + r];
+        for (int c = 0; c < 3; ++c) J[r][c] += X * d[c];
+      }
+    }
+    const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                       J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                       J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    ok &= det > 0.0;
+    if (gauss) {
+      const double id = 1.0 / det;
+      double Ji[9];
+      Ji[0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) * id;
+      Ji[1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+      Ji[2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+      Ji[3] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) * id;
+      Ji[4] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+      Ji[5] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+      Ji[6] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) * id;
+      Ji[7] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+      Ji[8] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+      const size_t o = ((size_t)e * kQ2Nodes + q) * 10;
+      const double w = q2_gw(qi) * q2_gw(qj) * q2_gw(qk);
+      for (int k = 0; k < 9; ++k) {
+        geo[o + k] = Ji[k];
+        geo32[o + k] = float(Ji[k]);
+      }
+      geo[o + 9] = w * det;
+      geo32[o + 9] = float(w * det);
+    } else {
+      const double gl[3] = {1.0 / 3.0, 4.0 / 3.0, 1.0 / 3.0};
+      vdet[(size_t)e * kQ2Nodes + q] = gl[qi] * gl[qj] * gl[qk] * det;
+    }
+  }
+  if (!ok) atomicOr(bad, 1);
+}
+
 // flag elements whose Gauss-point geometry differs from element 0's
 // An element is congruent to element 0 when every J^{-1} entry agrees to `tol` of the
 // largest J^{-1} entry of that quadrature point (entries that vanish in exact arithmetic
 // carry rounding noise) and det J agrees to `tol` relative.  The host sets tol from the
 // representation noise of the node coordinates: an edge of length h between nodes at
 // distance R from the origin carries a relative error of about eps R / h.
-__global__ void k_congruence(const double* __restrict__ geo, int n_e, double tol, int* __restrict__ mismatch) {
+__global__ void k_congruence(const double* __restrict__ geo, int n_e, int nvals, double tol,
+                             int* __restrict__ mismatch) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)n_e * 80) return;
-  const int r = (int)(idx % 80);
+  if (idx >= (size_t)n_e * nvals) return;
+  const int r = (int)(idx % nvals);
   const int q = r / 10, k = r - q * 10;
   double scale = 0.0;
   if (k < 9) {
@@ -100,7 +160,7 @@ __global__ void k_congruence(const double* __restrict__ geo, int n_e, double tol
 }
 
 // lumped mass by the vertex rule, M_A = rho * sum of vertex det J of the elements around A
-__global__ void k_mass(int n_nodes, int n_e, const int* __restrict__ inc_ptr, const int* __restrict__ inc,
+__global__ void k_mass(int n_nodes, int n_e, int npe, const int* __restrict__ inc_ptr, const int* __restrict__ inc,
                        const double* __restrict__ vdet, double rho, const unsigned char* __restrict__ clamp,
                        double* __restrict__ mih, double* __restrict__ mh) {
   const int A = blockIdx.x * blockDim.x + threadIdx.x;
@@ -109,7 +169,7 @@ __global__ void k_mass(int n_nodes, int n_e, const int* __restrict__ inc_ptr, co
   for (int p = inc_ptr[A]; p < inc_ptr[A + 1]; ++p) {
     const int slot = inc[p];
     const int a = slot / n_e, e = slot - a * n_e;
-    m += vdet[(size_t)e * 8 + a];
+    m += vdet[(size_t)e * npe + a];
   }
   m *= rho;
   const double sq = sqrt(m);
@@ -152,6 +212,40 @@ __global__ void k_face_force(const double* __restrict__ xyz, const int* __restri
     ff[((size_t)f * 4 + b) * 3 + 0] = acc[b] * t0x;
     ff[((size_t)f * 4 + b) * 3 + 1] = acc[b] * t0y;
     ff[((size_t)f * 4 + b) * 3 + 2] = acc[b] * t0z;
+  }
+}
+
+// consistent nodal forces of a dead traction on biquadratic 9-node faces (node p + 3 q at
+// local (p-1, q-1)), 3x3 Gauss (weak-form term 3)
+__global__ void k_face_force9(const double* __restrict__ xyz, const int* __restrict__ faces, int n_f, double t0x,
+                              double t0y, double t0z, double* __restrict__ ff) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= n_f) return;
+  double X[9][3];
+  for (int b = 0; b < 9; ++b)
+    for (int i = 0; i < 3; ++i) X[b][i] = xyz[(size_t)faces[(size_t)f * 9 + b] * 3 + i];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int g = 0; g < 9; ++g) {
+    const double s = q2_gpt(g % 3), t = q2_gpt(g / 3), wq = q2_gw(g % 3) * q2_gw(g / 3);
+    double a1[3] = {0, 0, 0}, a2[3] = {0, 0, 0};
+    for (int b = 0; b < 9; ++b) {
+      const double dNs = dlag3(b % 3, s) * lag3(b / 3, t);
+      const double dNt = lag3(b % 3, s) * dlag3(b / 3, t);
+      for (int i = 0; i < 3; ++i) {
+        a1[i] += dNs * X[b][i];
+        a2[i] += dNt * X[b][i];
+      }
+    }
+    const double cx = a1[1] * a2[2] - a1[2] * a2[1];
+    const double cy = a1[2] * a2[0] - a1[0] * a2[2];
+    const double cz = a1[0] * a2[1] - a1[1] * a2[0];
+    const double dA = wq * sqrt(cx * cx + cy * cy + cz * cz);
+    for (int b = 0; b < 9; ++b) acc[b] += lag3(b % 3, s) * lag3(b / 3, t) * dA;
+  }
+  for (int b = 0; b < 9; ++b) {
+    ff[((size_t)f * 9 + b) * 3 + 0] = acc[b] * t0x;
+    ff[((size_t)f * 9 + b) * 3 + 1] = acc[b] * t0y;
+    ff[((size_t)f * 9 + b) * 3 + 2] = acc[b] * t0z;
   }
 }
 
@@ -230,6 +324,15 @@ __global__ __launch_bounds__(256, 2) void k_elem_forces(Mesh M, OpArgs op, const
     store_force(M, e, f, F);
   }
   if (!ok) atomicCAS(err, 0, kErrInverted);
+}
+
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_elem_forces_q2(Mesh M, OpArgs op, const double* __restrict__ src,
+                                                        double srcscale, int scale_mih, T* __restrict__ F,
+                                                        int* __restrict__ err) {
+  const int e = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) / kQ2Lanes);
+  if (e >= M.n_elems) return;     // whole 32-lane groups leave together
+  if (!elem_force_q2<T, MODEL>(M, op, e, src, srcscale, scale_mih != 0, F)) atomicCAS(err, 0, kErrInverted);
 }
 
 template <typename T>
@@ -357,6 +460,36 @@ __global__ __launch_bounds__(256) void k_energy_elem(Mesh M, const double* __res
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+template <int MODEL>
+__global__ __launch_bounds__(256) void k_energy_elem27(Mesh M, const double* __restrict__ S,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[16];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (e < M.n_elems) {
+    for (int q = 0; q < kQ2Nodes; ++q) {
+      const size_t gi = (M.congruent ? (size_t)q : (size_t)e * kQ2Nodes + q) * 10;
+      double Dxi[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int a = 0; a < kQ2Nodes; ++a) {
+        double d[3];
+        q2_dN(a, q, d);
+        const int n = M.conn[(size_t)e * kQ2Nodes + a];
+        for (int i = 0; i < 3; ++i) {
+          const double u = M.mih[(size_t)n * 3 + i] * S[(size_t)n * 3 + i];
+          for (int j = 0; j < 3; ++j) Dxi[i][j] += u * d[j];
+        }
+      }
+      double D[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          D[i][k] = Dxi[i][0] * M.geo[gi + k] + Dxi[i][1] * M.geo[gi + 3 + k] + Dxi[i][2] * M.geo[gi + 6 + k];
+      acc += M.geo[gi + 9] * psi_at<MODEL>(D, M.mp);
+    }
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(256) void k_energy_vec(int n3, const double* __restrict__ S,
                                                     const double* __restrict__ p0bar, double* __restrict__ partial) {
   __shared__ double red[16];
@@ -455,20 +588,25 @@ hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
 // ---------------------------------------------------------------------------------------
 static inline int nblk(long long n, int b) { return (int)((n + b - 1) / b); }
 
-void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,
-                     hipStream_t st) {
-  if (n_e > 0) k_geometry<<<nblk(n_e, 128), 128, 0, st>>>(xyz, conn, n_e, geo, geo32, vdet, bad);
+void launch_geometry(const double* xyz, const int* conn, int n_e, int npe, double* geo, float* geo32, double* vdet,
+                     int* bad, hipStream_t st) {
+  if (n_e <= 0) return;
+  if (npe == kQ2Nodes) k_geometry27<<<nblk(n_e, 64), 64, 0, st>>>(xyz, conn, n_e, geo, geo32, vdet, bad);
+  else k_geometry<<<nblk(n_e, 128), 128, 0, st>>>(xyz, conn, n_e, geo, geo32, vdet, bad);
 }
-void launch_congruence(const double* geo, int n_e, double tol, int* mismatch, hipStream_t st) {
-  if (n_e > 0) k_congruence<<<nblk((long long)n_e * 80, 256), 256, 0, st>>>(geo, n_e, tol, mismatch);
+void launch_congruence(const double* geo, int n_e, int npe, double tol, int* mismatch, hipStream_t st) {
+  const int nvals = 10 * npe;       // J^{-1} and w det J at each of the npe Gauss points
+  if (n_e > 0) k_congruence<<<nblk((long long)n_e * nvals, 256), 256, 0, st>>>(geo, n_e, nvals, tol, mismatch);
 }
-void launch_mass(int n_nodes, int n_e, const int* inc_ptr, const int* inc, const double* vdet, double rho,
+void launch_mass(int n_nodes, int n_e, int npe, const int* inc_ptr, const int* inc, const double* vdet, double rho,
                  const unsigned char* clamp, double* mih, double* mh, hipStream_t st) {
-  if (n_nodes > 0) k_mass<<<nblk(n_nodes, 256), 256, 0, st>>>(n_nodes, n_e, inc_ptr, inc, vdet, rho, clamp, mih, mh);
+  if (n_nodes > 0)
+    k_mass<<<nblk(n_nodes, 256), 256, 0, st>>>(n_nodes, n_e, npe, inc_ptr, inc, vdet, rho, clamp, mih, mh);
 }
-void launch_faces(const double* xyz, const int* faces, int n_f, const double* t0, double* ff, int n_nodes,
+void launch_faces(const double* xyz, const int* faces, int n_f, int nfn, const double* t0, double* ff, int n_nodes,
                   const int* finc_ptr, const int* finc, const double* mih, double* p0, double* p0bar, hipStream_t st) {
-  if (n_f > 0) k_face_force<<<nblk(n_f, 128), 128, 0, st>>>(xyz, faces, n_f, t0[0], t0[1], t0[2], ff);
+  if (n_f > 0 && nfn == 9) k_face_force9<<<nblk(n_f, 128), 128, 0, st>>>(xyz, faces, n_f, t0[0], t0[1], t0[2], ff);
+  else if (n_f > 0) k_face_force<<<nblk(n_f, 128), 128, 0, st>>>(xyz, faces, n_f, t0[0], t0[1], t0[2], ff);
   if (n_nodes > 0) k_face_gather<<<nblk(n_nodes, 256), 256, 0, st>>>(n_nodes, finc_ptr, finc, ff, mih, p0, p0bar);
 }
 void launch_set_state(int n3, int Lp, const double* mh, const double* u, const double* v, double s0, double* S,
@@ -483,8 +621,16 @@ void launch_reset_ctrl(Ctrl* c, hipStream_t st) { k_reset_ctrl<<<1, 1, 0, st>>>(
 template <typename T>
 static void elem_forces_t(const Mesh& M, const OpArgs& op, const double* src, double sc, int scale_mih, T* F, int* err,
                           hipStream_t st) {
-  const int nb = nblk((long long)M.n_elems * 8, 256);
   if (M.n_elems == 0) return;
+  if (M.npe == kQ2Nodes) {
+    const int nq = nblk((long long)M.n_elems * kQ2Lanes, 256);
+    if (M.model == kLinear) k_elem_forces_q2<T, kLinear><<<nq, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+    else if (M.model == kNH) k_elem_forces_q2<T, kNH><<<nq, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+    else if (M.model == kSVK) k_elem_forces_q2<T, kSVK><<<nq, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+    else k_elem_forces_q2<T, kYeoh><<<nq, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
+    return;
+  }
+  const int nb = nblk((long long)M.n_elems * 8, 256);
   if (M.model == kLinear) k_elem_forces<T, kLinear><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
   else if (M.model == kNH) k_elem_forces<T, kNH><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
   else if (M.model == kSVK) k_elem_forces<T, kSVK><<<nb, 256, 0, st>>>(M, op, src, sc, scale_mih, F, err);
@@ -794,7 +940,12 @@ int energy_vec_blocks(const Mesh& M) { return nblk(M.n3, 256); }
 
 void launch_energy(const Mesh& M, const double* S, double t, double* pe, double* pv, double* out, hipStream_t st) {
   const int ne = energy_blocks(M), nv = energy_vec_blocks(M);
-  if (ne > 0) {
+  if (ne > 0 && M.npe == kQ2Nodes) {
+    if (M.model == kLinear) k_energy_elem27<kLinear><<<ne, 256, 0, st>>>(M, S, pe);
+    else if (M.model == kNH) k_energy_elem27<kNH><<<ne, 256, 0, st>>>(M, S, pe);
+    else if (M.model == kSVK) k_energy_elem27<kSVK><<<ne, 256, 0, st>>>(M, S, pe);
+    else k_energy_elem27<kYeoh><<<ne, 256, 0, st>>>(M, S, pe);
+  } else if (ne > 0) {
     if (M.model == kLinear) k_energy_elem<kLinear><<<ne, 256, 0, st>>>(M, S, pe);
     else if (M.model == kNH) k_energy_elem<kNH><<<ne, 256, 0, st>>>(M, S, pe);
     else if (M.model == kSVK) k_energy_elem<kSVK><<<ne, 256, 0, st>>>(M, S, pe);

@@ -14,12 +14,13 @@ const void* expv_kernel_global(int prec, int model, int ortho);
 const void* expv_kernel_m4(int prec, int model, int ortho);
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
 
-void launch_geometry(const double* xyz, const int* conn, int n_e, double* geo, float* geo32, double* vdet, int* bad,
+void launch_geometry(const double* xyz, const int* conn, int n_e, int npe, double* geo, float* geo32, double* vdet,
+                     int* bad,
                      hipStream_t st);
-void launch_congruence(const double* geo, int n_e, double tol, int* mismatch, hipStream_t st);
-void launch_mass(int n_nodes, int n_e, const int* inc_ptr, const int* inc, const double* vdet, double rho,
+void launch_congruence(const double* geo, int n_e, int npe, double tol, int* mismatch, hipStream_t st);
+void launch_mass(int n_nodes, int n_e, int npe, const int* inc_ptr, const int* inc, const double* vdet, double rho,
                  const unsigned char* clamp, double* mih, double* mh, hipStream_t st);
-void launch_faces(const double* xyz, const int* faces, int n_f, const double* t0, double* ff, int n_nodes,
+void launch_faces(const double* xyz, const int* faces, int n_f, int nfn, const double* t0, double* ff, int n_nodes,
                   const int* finc_ptr, const int* finc, const double* mih, double* p0, double* p0bar, hipStream_t st);
 void launch_set_state(int n3, int Lp, const double* mh, const double* u, const double* v, double s0, double* S,
                       hipStream_t st);

@@ -18,6 +18,7 @@
 
 #include "ep_device.hpp"
 #include "ep_expm.hpp"
+#include "ep_q2.hpp"
 #include "ep_tangent.hpp"
 
 namespace ep {
@@ -99,6 +100,12 @@ __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, 
           elem_force_ke(M, e, src, hinv, (const double*)ke, (double*)F);
         return true;
       }
+    }
+    if (M.npe == kQ2Nodes) {
+      // quadratic elements: 32 lanes per element, the loop bound uniform in each lane group
+      for (int e = (rank * blockDim.x + threadIdx.x) >> 5; e < M.n_elems; e += (G * blockDim.x) >> 5)
+        okA &= elem_force_q2<T, MODEL>(M, op, e, src, hinv, true, F);
+      return okA;
     }
     if (elem_lanes<T, MODEL>() == 8) {
       // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group

@@ -40,6 +40,7 @@ _SIGS = {
     "ep_version": [],
     "ep_set_stream": [_vp, _vp],
     "ep_set_mesh_hex8": [_vp, _i64, _vp, _i64, _vp],
+    "ep_set_mesh_hex27": [_vp, _i64, _vp, _i64, _vp],
     "ep_set_material": [_vp, C.c_int, _vp, C.c_int, _dbl],
     "ep_set_dirichlet": [_vp, _i64, _vp],
     "ep_set_traction": [_vp, _i64, _vp, _vp, _i64, _vp, _vp],
@@ -159,8 +160,10 @@ class Context:
 
     # ---------------------------------------------------------------- setup
     def set_mesh(self, xyz, conn):
+        """hex8 (conn n_e x 8) or quadratic 27-node hexahedra (conn n_e x 27)."""
         self._xyz, self._conn = _f64(xyz), _i32a(conn)
-        self._call("ep_set_mesh_hex8", self._xyz.shape[0], _ptr(self._xyz), self._conn.shape[0], _ptr(self._conn))
+        name = "ep_set_mesh_hex27" if self._conn.shape[1] == 27 else "ep_set_mesh_hex8"
+        self._call(name, self._xyz.shape[0], _ptr(self._xyz), self._conn.shape[0], _ptr(self._conn))
         self.n_nodes = self._xyz.shape[0]
 
     def set_material(self, model: str, params, rho: float):
@@ -172,7 +175,8 @@ class Context:
         self._call("ep_set_dirichlet", d.size, _ptr(d))
 
     def set_traction(self, faces, t0, knots_t, knots_s):
-        f = _i32a(faces).reshape(-1, 4)
+        f = _i32a(faces)
+        f = f.reshape(-1, f.shape[-1] if f.ndim == 2 else 4)
         t = _f64(t0)
         kt, ks = _f64(knots_t), _f64(knots_s)
         self._call("ep_set_traction", f.shape[0], _ptr(f), _ptr(t), kt.size, _ptr(kt), _ptr(ks))
