@@ -223,13 +223,16 @@ def run_matvec(prob, u_lin, reps, stream, torch, args):
     ctx.sync()
     us = e0.elapsed_time(e1) * 1e3 / (rounds * reps)
     workgroups, chunk, mesh_class = ctx.launch()
-    if prob.model == "linear" and mesh_class == 2:
+    npe = prob.conn.shape[1]
+    if npe == 27:
+        path, reads_conn = "Q2 element kernel (32 lanes per element) + slot gather", True
+    elif prob.model == "linear" and mesh_class == 2:
         path, reads_conn = "lattice: 27-block stencil over LDS tiles + boundary faces", False
     elif prob.model == "linear" and mesh_class == 1:
         path, reads_conn = "node-by-node, stored element stiffness", True
     else:
         path, reads_conn = "element kernel + slot gather", True
-    alg = (2 * n3 + (n3 if u is not None else 0)) * 8 + (32 * prob.n_elems if reads_conn else 0)
+    alg = (2 * n3 + (n3 if u is not None else 0)) * 8 + (4 * npe * prob.n_elems if reads_conn else 0)
     achieved = alg / (us * 1e-6) / 1e9
     log(args, f"  matvec {prob.name} {prob.model} {prob.grid}: {us:.2f} us/apply, {achieved:.0f} GB/s ({path})")
     del graph
@@ -619,6 +622,12 @@ def run_matvecs(config, stream, torch, args):
         del q
     u_aff = (0.02 * cube.xyz * np.array([1.0, 1.0, -1.0])).ravel()
     out["matvec_cube64_yeoh_f64"] = run_matvec(cube, u_aff, 20, stream, torch, args)
+    # the same 65^3 nodes as 32^3 quadratic (27-node) elements, the paper's element
+    from workloads import q2_of
+    q2 = q2_of(cube)
+    out["matvec_cube64nodes_q2_linear_f64"] = run_matvec(
+        dataclasses.replace(q2, model="linear", params=(200e9, 0.3), rho=7800.0), None, 20, stream, torch, args)
+    out["matvec_cube64nodes_q2_yeoh_f64"] = run_matvec(q2, u_aff, 20, stream, torch, args)
     return out
 
 

@@ -6,9 +6,10 @@
 // quadratic Lagrange polynomials l_0 = x(x-1)/2, l_1 = 1 - x^2, l_2 = x(x+1)/2.
 //
 // Element forces run on 32 lanes per element (lanes 0..26 active): lane q forms the
-// gradients and the stress at Gauss point q from the element's nodal values (taken from
-// lane a by shuffles), then lane a sums node a's force over the 27 points (their
-// w det J S J^{-T} taken by shuffles).  No LDS: the persistent Krylov kernel keeps its LDS
+// gradients and the stress at Gauss point q from the element's nodal values, then lane a
+// sums node a's force over the 27 points.  Both use sum factorisation over the
+// tensor-product basis (three one-dimensional contractions, the values of the lane's line
+// taken by shuffles).  No LDS: the persistent Krylov kernel keeps its LDS
 // for the basis slices.
 #pragma once
 
@@ -44,25 +45,68 @@ __device__ __forceinline__ T shfl_q2(T v, int src_lane) {
   return __shfl(v, src_lane, 64);
 }
 
-// Gradient at Gauss point q of the field whose nodal values lane a (< 27) of the 32-lane
-// group holds in va[3]: G[i][k] = sum_a va_i dN_a/dX_k with dN/dX = dN/dxi J^{-1}.
+// Select among three per-coordinate constants by the lane's coordinate c (0, 1, 2).
 template <typename T>
-__device__ __forceinline__ void q2_grad(const T (&va)[3], int q, int base, const T* Jinv, T (&G)[3][3]) {
+__device__ __forceinline__ T sel3(int c, double v0, double v1, double v2) {
+  return c == 0 ? T(v0) : (c == 1 ? T(v1) : T(v2));
+}
+// l_n(g_c) and l_n'(g_c): polynomial n (a compile-time index) at the lane's Gauss coordinate c
+template <typename T>
+__device__ __forceinline__ T lq(int n, int c) {
+  return sel3<T>(c, lag3(n, q2_gpt(0)), lag3(n, q2_gpt(1)), lag3(n, q2_gpt(2)));
+}
+template <typename T>
+__device__ __forceinline__ T dlq(int n, int c) {
+  return sel3<T>(c, dlag3(n, q2_gpt(0)), dlag3(n, q2_gpt(1)), dlag3(n, q2_gpt(2)));
+}
+// l_c(g_n) and l_c'(g_n): the lane's polynomial c at Gauss point n (a compile-time index)
+template <typename T>
+__device__ __forceinline__ T lp(int c, int n) {
+  return sel3<T>(c, lag3(0, q2_gpt(n)), lag3(1, q2_gpt(n)), lag3(2, q2_gpt(n)));
+}
+template <typename T>
+__device__ __forceinline__ T dlp(int c, int n) {
+  return sel3<T>(c, dlag3(0, q2_gpt(n)), dlag3(1, q2_gpt(n)), dlag3(2, q2_gpt(n)));
+}
+
+// Gradient at the lane's Gauss point (x, y, z) of the field whose nodal values lane
+// a = i + 3 j + 9 k of the group holds in va[3], by sum factorisation over the tensor-product
+// basis: contract along xi (value and derivative), then eta, then zeta, each step taking the
+// three values of the lane's line by shuffles (18 per component instead of 27 sums of 27).
+// G[i][k] = sum_a va_i dN_a/dX_k with dN/dX = dN/dxi J^{-1}.
+template <typename T>
+__device__ __forceinline__ void q2_grad(const T (&va)[3], int x, int y, int z, int base, const T* Jinv,
+                                        T (&G)[3][3]) {
   T Dxi[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 3; ++i) {
+    T a0 = T(0), a1 = T(0);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) Dxi[i][j] = T(0);
-  for (int a = 0; a < kQ2Nodes; ++a) {
-    T d[3];
-    q2_dN(a, q, d);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const T x = shfl_q2(va[i], base + a);
-      Dxi[i][0] += x * d[0];
-      Dxi[i][1] += x * d[1];
-      Dxi[i][2] += x * d[2];
+    for (int n = 0; n < 3; ++n) {
+      const T v = shfl_q2(va[i], base + n + 3 * y + 9 * z);
+      a0 += v * lq<T>(n, x);
+      a1 += v * dlq<T>(n, x);
     }
+    T bx = T(0), by = T(0), bz = T(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int src = base + x + 3 * n + 9 * z;
+      const T p0 = shfl_q2(a0, src), p1 = shfl_q2(a1, src);
+      bx += p1 * lq<T>(n, y);
+      by += p0 * dlq<T>(n, y);
+      bz += p0 * lq<T>(n, y);
+    }
+    T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int src = base + x + 3 * y + 9 * n;
+      gx += shfl_q2(bx, src) * lq<T>(n, z);
+      gy += shfl_q2(by, src) * lq<T>(n, z);
+      gz += shfl_q2(bz, src) * dlq<T>(n, z);
+    }
+    Dxi[i][0] = gx;
+    Dxi[i][1] = gy;
+    Dxi[i][2] = gz;
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -81,6 +125,7 @@ __device__ __forceinline__ bool elem_force_q2(const Mesh& M, const OpArgs& op, i
   const int l = threadIdx.x & (kQ2Lanes - 1), base = (threadIdx.x & 63) & ~(kQ2Lanes - 1);
   const bool act = l < kQ2Nodes;
   const int a = act ? l : 0;
+  const int cx = a % 3, cy = (a / 3) % 3, cz = a / 9;
   const int nd = M.conn[(size_t)e * kQ2Nodes + a];
   constexpr bool shift = sizeof(T) == 4;
   // nodal values of this lane's node: the input and the secant sets' displacements
@@ -118,7 +163,7 @@ __device__ __forceinline__ bool elem_force_q2(const Mesh& M, const OpArgs& op, i
   }
   if (!act) wdet = T(0);
   T X[3][3];
-  q2_grad(xa, q, base, Jinv, X);
+  q2_grad(xa, cx, cy, cz, base, Jinv, X);
   T S[3][3];
   bool ok = true;
   if (nsets == 0) {
@@ -137,7 +182,7 @@ __device__ __forceinline__ bool elem_force_q2(const Mesh& M, const OpArgs& op, i
       for (int k = 0; k < 3; ++k) S[i][k] = T(0);
     for (int s = 0; s < nsets; ++s) {
       T Du[3][3];
-      q2_grad(ua[s], q, base, Jinv, Du);
+      q2_grad(ua[s], cx, cy, cz, base, Jinv, Du);
       if constexpr (MODEL == kSVK) {
         double lam_d, mu_d;
         rest_lame(kSVK, M.mp, lam_d, mu_d);
@@ -155,15 +200,33 @@ __device__ __forceinline__ bool elem_force_q2(const Mesh& M, const OpArgs& op, i
 #pragma unroll
     for (int j = 0; j < 3; ++j)
       St[3 * i + j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
-  // ---- lane = node a: f_a,i = sum_q sum_j St_q[i][j] dN_a/dxi_j(q)
-  T f[3] = {T(0), T(0), T(0)};
-  for (int qq = 0; qq < kQ2Nodes; ++qq) {
-    T d[3];
-    q2_dN(a, qq, d);
+  // ---- lane = node a: f_a,i = sum_q sum_d St_q[i][d] dN_a/dxi_d(q), the transposed sum
+  // factorisation: contract the Gauss points along zeta, then eta, then xi
+  T f[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-      f[i] += shfl_q2(St[3 * i], base + qq) * d[0] + shfl_q2(St[3 * i + 1], base + qq) * d[1] +
-              shfl_q2(St[3 * i + 2], base + qq) * d[2];
+  for (int i = 0; i < 3; ++i) {
+    T t0 = T(0), t1 = T(0), t2 = T(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int src = base + cx + 3 * cy + 9 * n;
+      t0 += shfl_q2(St[3 * i], src) * lp<T>(cz, n);
+      t1 += shfl_q2(St[3 * i + 1], src) * lp<T>(cz, n);
+      t2 += shfl_q2(St[3 * i + 2], src) * dlp<T>(cz, n);
+    }
+    T u0 = T(0), v = T(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int src = base + cx + 3 * n + 9 * cz;
+      u0 += shfl_q2(t0, src) * lp<T>(cy, n);
+      v += shfl_q2(t1, src) * dlp<T>(cy, n) + shfl_q2(t2, src) * lp<T>(cy, n);
+    }
+    T fi = T(0);
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const int src = base + n + 3 * cy + 9 * cz;
+      fi += shfl_q2(u0, src) * dlp<T>(cx, n) + shfl_q2(v, src) * lp<T>(cx, n);
+    }
+    f[i] = fi;
   }
   if (act) {
 #pragma unroll
