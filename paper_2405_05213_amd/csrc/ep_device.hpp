@@ -904,16 +904,69 @@ __device__ __forceinline__ void node_force_ke(const Mesh& M, int A, const double
   f[2] = s2;
 }
 
+// Node -> element-slot map of an operator pass, set up once per pass.  Lattice meshes
+// (elements i-fastest, VTK corners, slot indices below 2^31) find the slots by index
+// arithmetic: corner a of the element whose origin is node - offset(a), in increasing a,
+// which is the order of the node's incidence list, so both forms add the same terms in the
+// same order.  Otherwise the node's incidence list is read.
+struct SlotMap {
+  const int* inc_ptr;
+  const int* inc;
+  bool lat;
+  int nx, ny, nz, NX, NXY;
+  double rNX, rNXY;           // 1/NX, 1/NXY: (A + 1/2) / N rounds to the exact quotient for A < 2^51
+  int base[8];                // slot of corner a of the element at the node, minus that element
+};
+
+__device__ __forceinline__ SlotMap slot_map(const Mesh& M) {
+  SlotMap S;
+  S.inc_ptr = M.inc_ptr;
+  S.inc = M.inc;
+  S.lat = M.lat[0] > 0 && (long long)M.n_elems * 24 < (1LL << 31);
+  S.nx = M.lat[0];
+  S.ny = M.lat[1];
+  S.nz = M.lat[2];
+  S.NX = S.nx + 1;
+  S.NXY = S.NX * (S.ny + 1);
+  S.rNX = 1.0 / (double)max(S.NX, 1);
+  S.rNXY = 1.0 / (double)max(S.NXY, 1);
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+    S.base[a] = a * M.n_elems - ((((a + 1) >> 1) & 1) + S.nx * (((a >> 1) & 1) + S.ny * (a >> 2)));
+  return S;
+}
+
 // sum of element-slot forces of DOF 3*A + c over the elements around node A
-// (slot indices, then forces, are loaded 8 at a time so that the loads overlap)
 template <typename T>
-__device__ __forceinline__ double gather_force(const Mesh& M, const T* F, int A, int c) {
+__device__ __forceinline__ double gather_slots(const SlotMap& S, const T* F, int A, int c) {
+  if (S.lat) {
+    const int k = (int)(((double)A + 0.5) * S.rNXY);
+    const int r = A - k * S.NXY;
+    const int j = (int)(((double)r + 0.5) * S.rNX);
+    const int i = r - j * S.NX;
+    const int e0 = i + S.nx * (j + S.ny * k);       // the element with its origin at the node
+    const bool x0 = i < S.nx, x1 = i > 0, y0 = j < S.ny, y1 = j > 0, z0 = k < S.nz, z1 = k > 0;
+    T f[8];
+    bool in[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const bool di = ((a + 1) >> 1) & 1, dj = (a >> 1) & 1, dk = a >> 2;
+      in[a] = (di ? x1 : x0) && (dj ? y1 : y0) && (dk ? z1 : z0);
+      f[a] = in[a] ? F[(e0 + S.base[a]) * 3 + c] : T(0);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (in[a]) s += double(f[a]);
+    return s;
+  }
+  // slot indices, then forces, loaded 8 at a time so that the loads overlap
   double s = 0.0;
-  const int p0 = M.inc_ptr[A], p1 = M.inc_ptr[A + 1];
+  const int p0 = S.inc_ptr[A], p1 = S.inc_ptr[A + 1];
   for (int p = p0; p < p1; p += 8) {
     int sl[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) sl[u] = p + u < p1 ? M.inc[p + u] : -1;
+    for (int u = 0; u < 8; ++u) sl[u] = p + u < p1 ? S.inc[p + u] : -1;
     T f[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) f[u] = sl[u] >= 0 ? F[(size_t)sl[u] * 3 + c] : T(0);
@@ -922,6 +975,11 @@ __device__ __forceinline__ double gather_force(const Mesh& M, const T* F, int A,
       if (sl[u] >= 0) s += double(f[u]);
   }
   return s;
+}
+
+template <typename T>
+__device__ __forceinline__ double gather_force(const Mesh& M, const T* F, int A, int c) {
+  return gather_slots(slot_map(M), F, A, c);
 }
 
 // load scale(t): piecewise linear through the knots, constant outside

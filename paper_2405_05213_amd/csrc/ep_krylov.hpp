@@ -58,6 +58,11 @@ struct KLds {
 // the kernel's register allocation into spills.
 constexpr int kPF = 4;
 
+// Entries per thread whose loads a slice loop issues before their stores.  The slices may
+// sit in LDS or in device memory behind one generic pointer, so a store can alias any later
+// load and would otherwise hold back the next entry's loads for a full memory round trip.
+constexpr int kLB = 4;
+
 __device__ __forceinline__ void prefetch_row(double (&pf)[kPF], const double* row, int nloc) {
 #pragma unroll
   for (int r = 0; r < kPF; ++r) {
@@ -143,18 +148,18 @@ __device__ __forceinline__ bool phase_elements_m4(const Mesh& M, const OpArgs& o
 //   u-part  dt x_v - M^{-1/2} Fu - c xs (p_2 - p_1)
 //   v-part  -M^{-1/2} Fv + dt/2 xs (p_1 + p_2)        (linear: -dt M^{-1/2} K M^{-1/2} x_u)
 template <typename T, int MODEL>
-__device__ __forceinline__ double m4_entry(const Mesh& M, const OpArgs& op, const T* F, const T* F2,
-                                           const double* src, double hinv, double xs, double ps1, double ps2,
-                                           double f, int g) {
+__device__ __forceinline__ double m4_entry(const Mesh& M, const SlotMap& sm, const OpArgs& op, const T* F,
+                                           const T* F2, const double* src, double hinv, double xs, double ps1,
+                                           double ps2, double f, int g) {
   const int n3 = M.n3;
   if (g < n3) {
     double w = op.dt4 * (src[n3 + g] * hinv) - op.c4 * xs * (ps2 - ps1) * M.p0bar[g];
-    if constexpr (MODEL != kLinear) w -= M.mih[g] * gather_force(M, F2, g / 3, g - (g / 3) * 3);
+    if constexpr (MODEL != kLinear) w -= M.mih[g] * gather_slots(sm, F2, g / 3, g - (g / 3) * 3);
     return f * w;
   }
   if (g < 2 * n3) {
     const int d = g - n3;
-    const double s = gather_force(M, F, d / 3, d - (d / 3) * 3);
+    const double s = gather_slots(sm, F, d / 3, d - (d / 3) * 3);
     const double sc = MODEL == kLinear ? op.dt4 : 1.0;
     return f * (-M.mih[d] * sc * s + 0.5 * op.dt4 * xs * (ps1 + ps2) * M.p0bar[d]);
   }
@@ -248,7 +253,19 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
   double hinv = 1.0 / beta;
   const double* src = W.X;
-  for (int i = threadIdx.x; i < nloc; i += blockDim.x) W.V[c0 + i] = W.X[c0 + i] * hinv;
+  for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
+    double x[kLB];
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int i = i0 + u * blockDim.x;
+      x[u] = i < nloc ? W.X[c0 + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kLB; ++u) {
+      const int i = i0 + u * blockDim.x;
+      if (i < nloc) W.V[c0 + i] = x[u] * hinv;
+    }
+  }
   double hmax = 0.0;
 
   for (int j = 1; j <= mcap; ++j) {
@@ -265,25 +282,38 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     R.nmv += 1;
     // ---- part 2 (own slice): w = f A v_{j-1}; fused with the first projection
     const double xs = src[2 * n3] * hinv * M.s_inv;      // s-entry of v_{j-1} / s0
+    const SlotMap sm = slot_map(M);                       // not held across the element pass
     double part = 0.0;
-    for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
-      const int g = c0 + i;
-      double w;
-      if constexpr (SCH == 4) {
-        w = m4_entry<T, MODEL>(M, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
-      } else if (g < n3) {
-        w = f * (src[n3 + g] * hinv);
-      } else if (g < 2 * n3) {
-        const int d = g - n3;
-        const double s = gather_force(M, F, d / 3, d - (d / 3) * 3);
-        w = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
-      } else {
-        w = 0.0;
+    for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
+      double w[kLB], v0[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int i = i0 + u * blockDim.x;
+        w[u] = 0.0;
+        v0[u] = 0.0;
+        if (i < nloc) {
+          const int g = c0 + i;
+          if constexpr (SCH == 4) {
+            w[u] = m4_entry<T, MODEL>(M, sm, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
+          } else if (g < n3) {
+            w[u] = f * (src[n3 + g] * hinv);
+          } else if (g < 2 * n3) {
+            const int d = g - n3;
+            const double s = gather_slots(sm, F, d / 3, d - (d / 3) * 3);
+            w[u] = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
+          }
+          v0[u] = W.V[c0 + i];
+        }
       }
-      lw[i] = w;
-      const double v0 = W.V[c0 + i];
-      lv[i] = v0;
-      part += w * v0;
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int i = i0 + u * blockDim.x;
+        if (i < nloc) {
+          lw[i] = w[u];
+          lv[i] = v0[u];
+          part += w[u] * v0[u];
+        }
+      }
     }
     // the next basis slice is loaded while each reduction is in flight
     // prefetch only in the linear kernels (reduction-latency bound); the secant-material
@@ -315,12 +345,27 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
           }
         } else {
           const double* Vi = W.V + (size_t)i * Lp + c0;
-          for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-            const double w = lw[t] - hprev * lv[t];
-            lw[t] = w;
-            const double vi = Vi[t];
-            lv[t] = vi;
-            part += w * vi;
+          for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
+            double a[kLB], b[kLB], q[kLB];
+#pragma unroll
+            for (int u = 0; u < kLB; ++u) {
+              const int t = t0 + u * blockDim.x;
+              if (t < nloc) {
+                a[u] = lw[t];
+                b[u] = lv[t];
+                q[u] = Vi[t];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < kLB; ++u) {
+              const int t = t0 + u * blockDim.x;
+              if (t < nloc) {
+                const double w = a[u] - hprev * b[u];
+                lw[t] = w;
+                lv[t] = q[u];
+                part += w * q[u];
+              }
+            }
           }
         }
         hp = tm.post(part, red, flag, false);
@@ -332,11 +377,26 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
         finite &= fabs(h) < INFINITY;
         hprev = h;
       } else {
-        for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-          const double w = lw[t] - hprev * lv[t];
-          lw[t] = w;
-          W.Wun[c0 + t] = w;
-          part += w * w;
+        for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
+          double a[kLB], b[kLB];
+#pragma unroll
+          for (int u = 0; u < kLB; ++u) {
+            const int t = t0 + u * blockDim.x;
+            if (t < nloc) {
+              a[u] = lw[t];
+              b[u] = lv[t];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kLB; ++u) {
+            const int t = t0 + u * blockDim.x;
+            if (t < nloc) {
+              const double w = a[u] - hprev * b[u];
+              lw[t] = w;
+              W.Wun[c0 + t] = w;
+              part += w * w;
+            }
+          }
         }
         hn = sqrt(tm.allreduce(part, red, flag, true));
         if (tm.dead) return R;
@@ -351,7 +411,19 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     if (!breakdown) {
       hinv = 1.0 / hn;
       double* Vj = W.V + (size_t)j * Lp + c0;
-      for (int t = threadIdx.x; t < nloc; t += blockDim.x) Vj[t] = lw[t] * hinv;
+      for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
+        double a[kLB];
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int t = t0 + u * blockDim.x;
+          a[u] = t < nloc ? lw[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int t = t0 + u * blockDim.x;
+          if (t < nloc) Vj[t] = a[u] * hinv;
+        }
+      }
     }
     bool check;
     if (cfg.m_fixed > 0) check = breakdown || j == cfg.m_fixed;
@@ -412,21 +484,31 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     R.nmv += 1;
     // w = f A v_{j-1} on the own slice
     const double xs = src[2 * n3] * hinv * M.s_inv;
-    for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
-      const int g = c0 + i;
-      double w;
-      if constexpr (SCH == 4) {
-        w = m4_entry<T, MODEL>(M, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
-      } else if (g < n3) {
-        w = f * (src[n3 + g] * hinv);
-      } else if (g < 2 * n3) {
-        const int d = g - n3;
-        const double s = gather_force(M, F, d / 3, d - (d / 3) * 3);
-        w = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
-      } else {
-        w = 0.0;
+    const SlotMap sm = slot_map(M);
+    for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
+      double w[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int i = i0 + u * blockDim.x;
+        w[u] = 0.0;
+        if (i < nloc) {
+          const int g = c0 + i;
+          if constexpr (SCH == 4) {
+            w[u] = m4_entry<T, MODEL>(M, sm, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
+          } else if (g < n3) {
+            w[u] = f * (src[n3 + g] * hinv);
+          } else if (g < 2 * n3) {
+            const int d = g - n3;
+            const double s = gather_slots(sm, F, d / 3, d - (d / 3) * 3);
+            w[u] = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
+          }
+        }
       }
-      lw[i] = w;
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int i = i0 + u * blockDim.x;
+        if (i < nloc) lw[i] = w[u];
+      }
     }
     __syncthreads();
     // partial inner products b_k = <v_k, w> (k < j) and l_k = <v_k, v_{j-1}> (k < j - 1):
@@ -544,10 +626,22 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     if (!breakdown) {
       hinv = 1.0 / hn;
       double* Vj = W.V + (size_t)j * Lp + c0;
-      for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-        const double v = lw[t] * hinv;
-        Vj[t] = v;
-        lv[t] = v;
+      for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
+        double a[kLB];
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int t = t0 + u * blockDim.x;
+          a[u] = t < nloc ? lw[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kLB; ++u) {
+          const int t = t0 + u * blockDim.x;
+          if (t < nloc) {
+            const double v = a[u] * hinv;
+            Vj[t] = v;
+            lv[t] = v;
+          }
+        }
       }
     }
     bool check;
@@ -588,10 +682,21 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
   double last_eps = 0.0;
   for (;;) {
     double part = 0.0;
-    for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
-      const double v = A.x_in[c0 + i];
-      W.X[c0 + i] = v;
-      part += v * v;
+    for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
+      double x[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int i = i0 + u * blockDim.x;
+        x[u] = i < nloc ? A.x_in[c0 + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        const int i = i0 + u * blockDim.x;
+        if (i < nloc) {
+          W.X[c0 + i] = x[u];
+          part += x[u] * x[u];
+        }
+      }
     }
     double beta = sqrt(tm.allreduce(part, red, flag, true));
     if (tm.dead) return;
