@@ -938,7 +938,7 @@ ep_status ep_bind_workspace(ep_ctx* c, void* p, size_t bytes) {
     for (;;) {
       if (c->cfg.scheme == 4 && sg)
         return fail(c, EP_ERR_ARG, "the fourth-order scheme needs the Krylov slices in LDS (team too small)");
-      EP_HIP(c, expv_max_blocks(c->cfg, c->one.model, chunk, sg, &bpc));
+      EP_HIP(c, expv_max_blocks(c->cfg, c->one.model, c->one.npe, chunk, sg, &bpc));
       if ((long long)bpc * c->cus >= G || G == 1) break;
       G = std::max(1, (int)((long long)bpc * c->cus));
       chunk = chunk_of(c, c->one, G, &sg);
@@ -1283,7 +1283,7 @@ ep_status ep_autotune(ep_ctx* c, double dt, int m_trial, int trials, int* best_G
     int sg = 0;
     const int chunk = chunk_of(c, I, G, &sg);
     int bpc = 0;
-    if (expv_max_blocks(c->cfg, I.model, chunk, sg, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
+    if (expv_max_blocks(c->cfg, I.model, I.npe, chunk, sg, &bpc) != hipSuccess || (long long)bpc * c->cus < G) continue;
     a.W.G = G;
     a.W.chunk = chunk;
     a.W.slices_global = sg;

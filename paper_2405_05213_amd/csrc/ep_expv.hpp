@@ -20,7 +20,8 @@ __host__ __device__ inline size_t expv_head_doubles(int ortho, int m_max) {
 // SG = 1: the workgroup's slices of w and of the newest basis vector live in device memory
 // (W.wscr, [w | v] rows of Lp doubles) and U holds only the expm scratch.
 // SCH = 4: the operator of the fourth-order scheme (Omega of the two-term Magnus series).
-template <typename T, int MODEL, int ORTHO, int SG, int SCH = 2>
+// NPE = 27: quadratic (27-node) elements.
+template <typename T, int MODEL, int ORTHO, int SG, int SCH = 2, int NPE = 8>
 __global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   extern __shared__ double lds[];
   const int C = A.W.chunk;
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(kExpvThreads) void k_expv(ExpvArgs A) {
   __syncthreads();
   GridTeam tm{(int)gridDim.x, (int)blockIdx.x, A.W.flags, A.W.ring, &A.W.ctrl->err, 0ull, 0u, false, 0u,
               A.W.vring, A.W.vw, 0u};
-  expv_body<T, MODEL, GridTeam, ORTHO, SCH>(tm, A, lw, lv, red, yb, flag, X);
+  expv_body<T, MODEL, GridTeam, ORTHO, SCH, NPE>(tm, A, lw, lv, red, yb, flag, X);
 }
 
 template <typename T, int MODEL, int SG>
@@ -72,6 +73,12 @@ template <typename T, int MODEL>
 inline const void* expv_fn_m4(int ortho) {
   return ortho == 1 ? reinterpret_cast<const void*>(&k_expv<T, MODEL, 1, 0, 4>)
                     : reinterpret_cast<const void*>(&k_expv<T, MODEL, 0, 0, 4>);
+}
+
+template <typename T, int MODEL, int SG>
+inline const void* expv_fn_q2(int ortho) {
+  return ortho == 1 ? reinterpret_cast<const void*>(&k_expv<T, MODEL, 1, SG, 2, 27>)
+                    : reinterpret_cast<const void*>(&k_expv<T, MODEL, 0, SG, 2, 27>);
 }
 
 template <int SG>

@@ -545,13 +545,38 @@ size_t expv_lds_bytes(int chunk, int ortho, int m_max, int sg) {
   return head + u;
 }
 
-static const void* expv_kernel(int prec, int model, int ortho, int sg, int scheme) {
+// Instantiations of the persistent projection kernel for quadratic (27-node) elements: kernels
+// of their own, so that the hex8 kernels carry no Q2 code (whose registers would otherwise
+// weigh on their allocation).  They are compiled in this translation unit: built in a unit of
+// their own, the FP64 linear-elastic compact-WY instance returned a zero state on a Q2
+// cantilever while the other seven matched the oracle (cause not found).
+template <int SG>
+static const void* q2_kernel(int prec, int model, int ortho) {
+  if (prec == 0) {
+    if (model == kLinear) return expv_fn_q2<double, kLinear, SG>(ortho);
+    if (model == kNH) return expv_fn_q2<double, kNH, SG>(ortho);
+    if (model == kSVK) return expv_fn_q2<double, kSVK, SG>(ortho);
+    return expv_fn_q2<double, kYeoh, SG>(ortho);
+  }
+  if (prec != 1) return nullptr;
+  if (model == kLinear) return expv_fn_q2<float, kLinear, SG>(ortho);
+  if (model == kNH) return expv_fn_q2<float, kNH, SG>(ortho);
+  if (model == kSVK) return expv_fn_q2<float, kSVK, SG>(ortho);
+  return expv_fn_q2<float, kYeoh, SG>(ortho);
+}
+
+static const void* expv_kernel_q2(int prec, int model, int ortho, int sg) {
+  return sg ? q2_kernel<1>(prec, model, ortho) : q2_kernel<0>(prec, model, ortho);
+}
+
+static const void* expv_kernel(int prec, int model, int npe, int ortho, int sg, int scheme) {
+  if (npe == kQ2Nodes) return scheme != 4 ? expv_kernel_q2(prec, model, ortho, sg) : nullptr;
   if (scheme == 4) return sg ? nullptr : expv_kernel_m4(prec, model, ortho);
   return sg ? expv_kernel_global(prec, model, ortho) : expv_kernel_sg<0>(prec, model, ortho);
 }
 
-hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int sg, int* blocks_per_cu) {
-  const void* fn = expv_kernel(cfg.prec, model, cfg.ortho, sg, cfg.scheme);
+hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int npe, int chunk, int sg, int* blocks_per_cu) {
+  const void* fn = expv_kernel(cfg.prec, model, npe, cfg.ortho, sg, cfg.scheme);
   if (fn == nullptr) return hipErrorInvalidValue;
   const size_t lds = expv_lds_bytes(chunk, cfg.ortho, cfg.m_max, sg);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -572,7 +597,7 @@ hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st) {
   const int nv = a.cfg.ortho == 1 ? kRing * a.W.G * a.W.vw : 0;
   const int n = nv > kRing * a.W.G ? nv : kRing * a.W.G;
   k_prep_team<<<(n + 255) / 256, 256, 0, st>>>(a.W.flags, a.W.ring, a.W.vring, a.W.G, nv);
-  const void* fn = expv_kernel(prec, a.M.model, a.cfg.ortho, a.W.slices_global, a.cfg.scheme);
+  const void* fn = expv_kernel(prec, a.M.model, a.M.npe, a.cfg.ortho, a.W.slices_global, a.cfg.scheme);
   if (fn == nullptr) return hipErrorInvalidValue;
   const size_t lds = expv_lds_bytes(a.W.chunk, a.cfg.ortho, a.cfg.m_max, a.W.slices_global);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

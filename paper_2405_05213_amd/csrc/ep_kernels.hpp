@@ -9,7 +9,7 @@ size_t expv_lds_bytes(int chunk, int ortho, int m_max, int sg);
 size_t expv_lds_head_bytes(int ortho, int m_max);
 void launch_stiffness(const Mesh& M, double* Ke, hipStream_t st);
 void launch_stencil_blocks(const double* Ke, double* B, hipStream_t st);
-hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int chunk, int sg, int* blocks_per_cu);
+hipError_t expv_max_blocks(const KrylovCfg& cfg, int model, int npe, int chunk, int sg, int* blocks_per_cu);
 const void* expv_kernel_global(int prec, int model, int ortho);
 const void* expv_kernel_m4(int prec, int model, int ortho);
 hipError_t launch_expv(const ExpvArgs& a, int prec, hipStream_t st);
