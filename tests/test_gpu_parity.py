@@ -239,7 +239,10 @@ def test_energy_conservation_free_vibration(prec, tol):
     conserves the discrete energy up to the Krylov tolerance (FP64: ~1e-8 measured) and the
     FP32 operator's rounding: 5e-6 - 1.6e-5 measured, depending on the adaptive path (small
     exponential implementations that agree to 1e-13 change the subspace size at some steps);
-    an element kernel that loses the deformation to a large common translation drifts 1e-3."""
+    an element kernel that loses the deformation to a large common translation drifts 1e-3.
+    The FP32 figure is not held to the 1e-6 energy gate of the batched rubber blocks: on this
+    stiff steel beam the FP32 operator itself is only accurate to 2-3e-6 (a bending field is a
+    small difference of large element forces), so the energy cannot be conserved below that."""
     say(f"[energy] c2 20x4x4 {prec}")
     p = config("c2", nx=20, ny=4, nz=4)
     ctx, _ = pair(p, precision=prec, m_max=64)
