@@ -217,6 +217,25 @@ ep_status ep_sync(ep_ctx* ctx);
 /* Synchronising reads.  u_host / v_host: 3*n_nodes doubles (clamped entries 0). */
 ep_status ep_get_state(ep_ctx* ctx, double* t, double* u_host, double* v_host);
 
+/* Checkpoint and resume.  A checkpoint is an opaque host image of the whole stepping state
+ * (Sec. 4.1-4.2: what the next step reads): t and the step count, the augmented state
+ * vector as held on the device (ubar = M^{1/2} u, vbar, s; not re-derived from u and v, so
+ * nothing is rounded), the predictor's midpoint displacements and which of them the next
+ * predictor extrapolates from, the adaptive Krylov state (sticky substep counts, subspace
+ * hints), the resolved augmented entry s0 and, for the fourth-order scheme, the previous
+ * step's start state.  ep_checkpoint_size gives the byte count (fixed for a bound
+ * context); ep_save_checkpoint fills a caller-owned host buffer of exactly that size
+ * (synchronising; fails with the sticky device error if one is pending, EP_ERR_ORDER
+ * before a state is set); ep_load_checkpoint restores it into this or another context bound
+ * for the same mesh size, element family, material model, precision and scheme (EP_ERR_ARG
+ * otherwise, and on a corrupt header) and clears the sticky error.  Steps after a load
+ * reproduce, bit for bit, the steps the saving context takes from the same point when both
+ * contexts run with the same team size (ep_get_launch); another team size sums the
+ * reductions in another order (results equal to rounding). */
+ep_status ep_checkpoint_size(ep_ctx* ctx, size_t* bytes);
+ep_status ep_save_checkpoint(ep_ctx* ctx, void* buf_host, size_t bytes);
+ep_status ep_load_checkpoint(ep_ctx* ctx, const void* buf_host, size_t bytes);
+
 /* Energies at the current state (Sec. 5.2 generalised): kinetic 1/2 v^T M v, strain
  * sum_e sum_q w detJ psi(F), and the work of the current load P(t)^T u. */
 ep_status ep_get_energy(ep_ctx* ctx, double* kinetic, double* strain, double* ext_work);
@@ -342,6 +361,13 @@ ep_status ep_batch_get_state(ep_ctx* ctx, int32_t instance_id, double* t, double
 ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs, int* last_m,
                              int* last_k, double* last_eps, int64_t* matvecs_pred, int* last_m_pred,
                              int* last_k_pred);
+/* Checkpoints of one instance, as ep_checkpoint_size / ep_save_checkpoint /
+ * ep_load_checkpoint (the save synchronises and returns that instance's failure only; a
+ * load needs a batch instance of the same sizes, material, precision). */
+ep_status ep_batch_checkpoint_size(ep_ctx* ctx, int32_t instance_id, size_t* bytes);
+ep_status ep_batch_save_checkpoint(ep_ctx* ctx, int32_t instance_id, void* buf_host, size_t bytes);
+ep_status ep_batch_load_checkpoint(ep_ctx* ctx, int32_t instance_id, const void* buf_host,
+                                   size_t bytes);
 /* Per-instance energies, as ep_get_energy. */
 ep_status ep_batch_get_energy(ep_ctx* ctx, int32_t instance_id, double* kinetic, double* strain,
                               double* ext_work);

@@ -1495,6 +1495,187 @@ ep_status ep_batch_get_state(ep_ctx* c, int32_t id, double* t, double* u, double
   return EP_OK;
 }
 
+// ------------------------------------------------------------------------- checkpoints
+// Opaque image of an instance's stepping state: a fixed header, then the device state vector
+// (Lp doubles: ubar | vbar | s | padding, as held), the predictor's three midpoint
+// displacement fields (3 n3 doubles), the fourth-order scheme's previous start state (2 n3
+// doubles, scheme 4 only) and the control block (adaptive Krylov state per projection kind).
+namespace {
+struct CkptHead {
+  char magic[8];
+  int32_t version, n3, Lp, npe, model, prec, scheme, batch;
+  int32_t nhist, hist_new, hist_old, s0_pending, m4_prev, G;
+  int64_t step_idx;
+  double t, t_prev, s0;
+};
+constexpr char kCkptMagic[8] = {'E', 'P', 'C', 'K', 'P', 'T', '0', '1'};
+}  // namespace
+
+static size_t ckpt_sprev(const ep_ctx* c, const Inst& I) { return c->cfg.scheme == 4 ? 2 * (size_t)I.n3 : 0; }
+
+static size_t ckpt_bytes(const ep_ctx* c, const Inst& I) {
+  return sizeof(CkptHead) + 8 * ((size_t)I.Lp + 3 * (size_t)I.n3 + ckpt_sprev(c, I)) + sizeof(Ctrl);
+}
+
+static ep_status ckpt_save(ep_ctx* c, Inst& I, CkptHead h, void* buf, size_t bytes) {
+  if (!buf) return fail(c, EP_ERR_ARG, "null checkpoint buffer");
+  if (bytes < ckpt_bytes(c, I)) return fail(c, EP_ERR_ARG, "checkpoint buffer too small");
+  if (!I.state_set) return fail(c, EP_ERR_ORDER, "no state to save: set a state first");
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.n3 = I.n3;
+  h.Lp = I.Lp;
+  h.npe = I.npe;
+  h.model = I.model;
+  h.prec = c->cfg.prec;
+  h.scheme = c->cfg.scheme == 4 ? 4 : 2;
+  h.G = I.W.G;
+  h.s0 = I.M.s0;
+  h.s0_pending = I.s0_pending ? 1 : 0;
+  char* p = static_cast<char*>(buf);
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  EP_HIP(c, hipMemcpy(p, dptr<double>(c, I.o_S), 8 * (size_t)I.Lp, hipMemcpyDeviceToHost));
+  p += 8 * (size_t)I.Lp;
+  EP_HIP(c, hipMemcpy(p, dptr<double>(c, I.o_hist), 8 * 3 * (size_t)I.n3, hipMemcpyDeviceToHost));
+  p += 8 * 3 * (size_t)I.n3;
+  if (ckpt_sprev(c, I)) {
+    EP_HIP(c, hipMemcpy(p, dptr<double>(c, I.o_Sprev), 8 * ckpt_sprev(c, I), hipMemcpyDeviceToHost));
+    p += 8 * ckpt_sprev(c, I);
+  }
+  EP_HIP(c, hipMemcpy(p, I.W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  return EP_OK;
+}
+
+// Checks the header against the instance and copies the device parts; returns the header.
+static ep_status ckpt_load(ep_ctx* c, Inst& I, const void* buf, size_t bytes, bool batch, CkptHead* out) {
+  if (!buf) return fail(c, EP_ERR_ARG, "null checkpoint buffer");
+  if (bytes < sizeof(CkptHead)) return fail(c, EP_ERR_ARG, "not a checkpoint");
+  CkptHead h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1) return fail(c, EP_ERR_ARG, "not a checkpoint");
+  if (bytes != ckpt_bytes(c, I)) return fail(c, EP_ERR_ARG, "checkpoint size does not match this instance");
+  if (h.n3 != I.n3 || h.Lp != I.Lp || h.npe != I.npe || h.model != I.model || h.prec != c->cfg.prec ||
+      h.scheme != (c->cfg.scheme == 4 ? 4 : 2) || h.batch != (batch ? 1 : 0))
+    return fail(c, EP_ERR_ARG, "checkpoint of a different mesh size, element, material, precision, scheme or "
+                               "context kind");
+  if (!(std::isfinite(h.t) && std::isfinite(h.s0) && h.s0 >= 0.0) || h.nhist < 0 || h.nhist > 2 ||
+      h.hist_new < -1 || h.hist_new > 2 || h.hist_old < -1 || h.hist_old > 2 || h.step_idx < 0)
+    return fail(c, EP_ERR_ARG, "corrupt checkpoint header");
+  const char* p = static_cast<const char*>(buf) + sizeof(h);
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  EP_HIP(c, hipMemcpy(dptr<double>(c, I.o_S), p, 8 * (size_t)I.Lp, hipMemcpyHostToDevice));
+  p += 8 * (size_t)I.Lp;
+  EP_HIP(c, hipMemcpy(dptr<double>(c, I.o_hist), p, 8 * 3 * (size_t)I.n3, hipMemcpyHostToDevice));
+  p += 8 * 3 * (size_t)I.n3;
+  if (ckpt_sprev(c, I)) {
+    EP_HIP(c, hipMemcpy(dptr<double>(c, I.o_Sprev), p, 8 * ckpt_sprev(c, I), hipMemcpyHostToDevice));
+    p += 8 * ckpt_sprev(c, I);
+  }
+  Ctrl ctl;
+  std::memcpy(&ctl, p, sizeof(Ctrl));
+  ctl.err = 0;
+  ctl.bar = 0;
+  EP_HIP(c, hipMemcpy(I.W.ctrl, &ctl, sizeof(Ctrl), hipMemcpyHostToDevice));
+  I.M.s0 = h.s0;
+  I.M.s_inv = h.s0 != 0.0 ? 1.0 / h.s0 : 0.0;
+  I.s0_pending = h.s0_pending != 0;
+  I.m4_prev = h.m4_prev != 0;
+  I.t_prev = h.t_prev;
+  I.state_set = true;
+  *out = h;
+  return EP_OK;
+}
+
+ep_status ep_checkpoint_size(ep_ctx* c, size_t* bytes) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  if (!bytes) return fail(c, EP_ERR_ARG, "null output");
+  *bytes = ckpt_bytes(c, c->one);
+  return EP_OK;
+}
+
+ep_status ep_save_checkpoint(ep_ctx* c, void* buf, size_t bytes) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  s = ep_sync(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  CkptHead h{};
+  h.batch = 0;
+  h.nhist = I.nhist;
+  h.hist_new = I.hist_new;
+  h.hist_old = I.hist_old;
+  h.m4_prev = I.m4_prev ? 1 : 0;
+  h.step_idx = I.step_idx;
+  h.t = I.t;
+  h.t_prev = I.t_prev;
+  return ckpt_save(c, I, h, buf, bytes);
+}
+
+ep_status ep_load_checkpoint(ep_ctx* c, const void* buf, size_t bytes) {
+  ep_status s = need_bound(c);
+  if (s != EP_OK) return s;
+  Inst& I = c->one;
+  CkptHead h;
+  s = ckpt_load(c, I, buf, bytes, false, &h);
+  if (s != EP_OK) return s;
+  I.t = h.t;
+  I.step_idx = h.step_idx;
+  I.nhist = h.nhist;
+  I.hist_new = h.hist_new;
+  I.hist_old = h.hist_old;
+  return EP_OK;
+}
+
+ep_status ep_batch_checkpoint_size(ep_ctx* c, int32_t id, size_t* bytes) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  if (!bytes) return fail(c, EP_ERR_ARG, "null output");
+  *bytes = ckpt_bytes(c, c->insts[id]);
+  return EP_OK;
+}
+
+ep_status ep_batch_save_checkpoint(ep_ctx* c, int32_t id, void* buf, size_t bytes) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  s = read_err(c, c->insts[id]);
+  if (s != EP_OK) return s;
+  s = pull_record(c, id);
+  if (s != EP_OK) return s;
+  const BatchInst& B = c->btab[id];
+  CkptHead h{};
+  h.batch = 1;
+  h.nhist = B.nhist;
+  h.hist_new = B.hist_new;
+  h.hist_old = B.hist_old;
+  h.step_idx = B.step_idx;
+  h.t = B.t;
+  return ckpt_save(c, c->insts[id], h, buf, bytes);
+}
+
+ep_status ep_batch_load_checkpoint(ep_ctx* c, int32_t id, const void* buf, size_t bytes) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  Inst& I = c->insts[id];
+  CkptHead h;
+  s = ckpt_load(c, I, buf, bytes, true, &h);
+  if (s != EP_OK) return s;
+  s = pull_record(c, id);
+  if (s != EP_OK) return s;
+  BatchInst& B = c->btab[id];
+  B.t = h.t;
+  B.step_idx = h.step_idx;
+  B.nhist = h.nhist;
+  B.hist_new = h.hist_new;
+  B.hist_old = h.hist_old;
+  B.M.s0 = I.M.s0;
+  B.M.s_inv = I.M.s_inv;
+  EP_HIP(c, hipMemcpy(dptr<BatchInst>(c, c->o_batch_tab) + id, &B, sizeof(BatchInst), hipMemcpyHostToDevice));
+  return EP_OK;
+}
+
 ep_status ep_batch_get_stats(ep_ctx* c, int32_t id, int64_t* matvecs, int* last_m, int* last_k, double* last_eps,
                              int64_t* matvecs_pred, int* last_m_pred, int* last_k_pred) {
   ep_status s = need_batch(c, id);

@@ -59,6 +59,9 @@ _SIGS = {
     "ep_sync": [_vp],
     "ep_get_state": [_vp, _P(_dbl), _vp, _vp],
     "ep_get_energy": [_vp, _P(_dbl), _P(_dbl), _P(_dbl)],
+    "ep_checkpoint_size": [_vp, _P(C.c_size_t)],
+    "ep_save_checkpoint": [_vp, _vp, C.c_size_t],
+    "ep_load_checkpoint": [_vp, _vp, C.c_size_t],
     "ep_get_stats": [_vp, _P(_i64), _P(C.c_int), _P(_dbl), _P(C.c_int), _P(_dbl)],
     "ep_get_step_log": [_vp, C.c_int, _vp, _vp, _vp, _vp],
     "ep_apply_H": [_vp, _vp, _vp, _vp],
@@ -77,6 +80,9 @@ _SIGS = {
     "ep_batch_get_stats": [_vp, _i32, _P(_i64), _P(C.c_int), _P(C.c_int), _P(_dbl), _P(_i64), _P(C.c_int),
                            _P(C.c_int)],
     "ep_batch_get_energy": [_vp, _i32, _P(_dbl), _P(_dbl), _P(_dbl)],
+    "ep_batch_checkpoint_size": [_vp, _i32, _P(C.c_size_t)],
+    "ep_batch_save_checkpoint": [_vp, _i32, _vp, C.c_size_t],
+    "ep_batch_load_checkpoint": [_vp, _i32, _vp, C.c_size_t],
 }
 EXPORTED = sorted(_SIGS)
 
@@ -251,6 +257,19 @@ class Context:
         self._call("ep_get_state", C.byref(t), _ptr(u), _ptr(v))
         return t.value, u, v
 
+    def save_checkpoint(self) -> bytes:
+        """Opaque image of the whole stepping state (ep_save_checkpoint)."""
+        n = C.c_size_t()
+        self._call("ep_checkpoint_size", C.byref(n))
+        buf = C.create_string_buffer(n.value)
+        self._call("ep_save_checkpoint", buf, n.value)
+        return buf.raw
+
+    def load_checkpoint(self, image: bytes):
+        """Resume from an image of save_checkpoint (ep_load_checkpoint)."""
+        buf = C.create_string_buffer(bytes(image), len(image))
+        self._call("ep_load_checkpoint", buf, len(image))
+
     def energy(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()
         self._call("ep_get_energy", C.byref(a), C.byref(b), C.byref(c))
@@ -350,6 +369,19 @@ class Batch(Context):
         u, v = np.empty(n), np.empty(n)
         self._call("ep_batch_get_state", int(iid), C.byref(t), _ptr(u), _ptr(v))
         return t.value, u, v
+
+    def save_checkpoint(self, iid) -> bytes:
+        """Opaque image of one instance's stepping state (ep_batch_save_checkpoint)."""
+        n = C.c_size_t()
+        self._call("ep_batch_checkpoint_size", int(iid), C.byref(n))
+        buf = C.create_string_buffer(n.value)
+        self._call("ep_batch_save_checkpoint", int(iid), buf, n.value)
+        return buf.raw
+
+    def load_checkpoint(self, iid, image: bytes):
+        """Resume one instance from an image of save_checkpoint (ep_batch_load_checkpoint)."""
+        buf = C.create_string_buffer(bytes(image), len(image))
+        self._call("ep_batch_load_checkpoint", int(iid), buf, len(image))
 
     def stats(self, iid):
         mv, m, k, e = C.c_int64(), C.c_int(), C.c_int(), C.c_double()
