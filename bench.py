@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--m-max", type=int, default=64)
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed_f32", "mixed_bf16"])
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="keep one workgroup per batch instance (no plan autotuning)")
     ap.add_argument("--ortho", type=int, default=-1, choices=[-1, 0, 1],
                     help="Gram-Schmidt form: -1 automatic, 0 sequential, 1 compact WY")
     ap.add_argument("--adaptive", action="store_true", help="keep the adaptive subspace choice while timing")
@@ -330,6 +332,16 @@ def run_batch(probs, precision, steps, warmup, m_max, stream, torch, args):
     from paper_2405_05213_amd.ep import S0_SCALED
     b = batch_from_problems(probs, m_max=m_max, precision=precision, stream=stream.cuda_stream, s0=S0_SCALED)
     dt = probs[0].dt
+    plan = None
+    if not getattr(args, "no_batch_autotune", False):
+        # the project's plan autotuner: teams of workgroups for the costly blocks, lists of
+        # cheap ones (states restored afterwards)
+        wg, tuned_ms = b.autotune(dt, steps=5)
+        teams = [b.plan_of(i)[0] for i in range(len(probs))]
+        plan = {"workgroups": wg, "max_team": max(teams), "instances_in_teams": sum(g > 1 for g in teams),
+                "autotune_ms_per_step": tuned_ms}
+        log(args, f"  batch {len(probs)} {precision}: plan {wg} workgroups, largest team {max(teams)}, "
+                  f"{plan['instances_in_teams']} instances in teams ({tuned_ms:.3f} ms/step while tuning)")
     b.step(dt, max(1, warmup))
     b.sync()
     st0 = [b.stats(i) for i in range(len(probs))]
@@ -361,7 +373,7 @@ def run_batch(probs, precision, steps, warmup, m_max, stream, torch, args):
         "matvecs_per_step": float(mv.sum()) / steps,
         "m_corr_range": [min(q[0] for q in per_inst), max(q[0] for q in per_inst)],
         "m_pred_range": [min(q[2] for q in per_inst), max(q[2] for q in per_inst)],
-        "alg_bytes_per_launch": alg, "wall_s": wall,
+        "alg_bytes_per_launch": alg, "wall_s": wall, "plan": plan,
     }
     b.close()
     return out

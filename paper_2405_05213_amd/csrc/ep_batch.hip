@@ -1,17 +1,19 @@
-// Batched instances (many independent meshes / materials / loads): one workgroup per
-// instance runs the whole predictor-corrector step of its instance, so the Krylov
-// reductions never leave the workgroup.  The stepping state lives in device records and
-// one launch advances every instance by one step, which makes the launch replayable from a
-// captured graph.
+// Batched instances (many independent meshes / materials / loads).  A workgroup either
+// steps a list of instances one after the other (their Krylov reductions never leave the
+// workgroup), or is one member of a team of workgroups that steps one large instance
+// together (the data-as-flag team of the single-instance kernel, with its bounded waits).
+// The host plans the assignment so that the launch's longest workgroup is as short as the
+// compute units allow.  The stepping state lives in device records and one launch advances
+// every instance by one step, which makes the launch replayable from a captured graph.
 #include "ep_kernels.hpp"
 #include "ep_krylov.hpp"
 
 namespace ep {
 
-// u = M^{-1/2} ubar over the team's slice, then a team barrier
+// u = M^{-1/2} ubar, each team member its share, then a team barrier
 template <class Team>
 __device__ void team_get_u(Team& tm, const Mesh& M, const double* S, double* u, int* flag) {
-  for (int d = threadIdx.x; d < M.n3; d += blockDim.x) u[d] = M.mih[d] * S[d];
+  for (int d = tm.rank * blockDim.x + threadIdx.x; d < M.n3; d += tm.G * blockDim.x) u[d] = M.mih[d] * S[d];
   tm.sync(flag);
 }
 
@@ -129,20 +131,17 @@ __device__ bool device_step(Team& tm, BatchInst& B, ExpvArgs& a, const KrylovCfg
 // doubles of LDS before the slice buffers: red[32] | yb[kMaxM] | ints flag[16], 16 unused
 constexpr int kBatchHead = 32 + kMaxM + 16;
 
-template <typename T, int MODEL>
-__global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* ids, KrylovCfg cfg, double dt,
-                                                    int n_steps, int lds_slices) {
-  extern __shared__ double lds[];
+// Steps of instance id by this workgroup (team tm), with B and a the workgroup's LDS copies
+// of its record and projection arguments.  Rank 0's lane 0 writes the stepping state back
+// and adds the steps' wall-clock ticks to the instance's control block.
+template <typename T, int MODEL, class Team>
+__device__ void run_instance(Team& tm, BatchInst* tab, int id, BatchInst& B, ExpvArgs& a, const KrylovCfg& cfg,
+                             double dt, int n_steps, double* lds, int lds_slices, int* flag) {
   double* red = lds;
   double* yb = lds + 32;
-  int* flag = (int*)(lds + 32 + kMaxM);
   // the slice region (lds_slices doubles) doubles as expm scratch: the sequential form
   // reloads both slice buffers after a check point
   const KLds X{nullptr, nullptr, nullptr, nullptr, lds + kBatchHead, lds_slices, true};
-  // the instance record and the projection arguments: one copy per workgroup in LDS
-  __shared__ BatchInst B;
-  __shared__ ExpvArgs a;
-  const int id = ids[blockIdx.x];
   if (threadIdx.x == 0) {
     *flag = 1;
     B = tab[id];
@@ -154,18 +153,57 @@ __global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const int* i
     lw = lds + kBatchHead;
     lv = lw + B.W.chunk;
   } else {
-    lw = B.W.wscr;
-    lv = B.W.wscr + B.M.Lp;
+    const size_t c0 = (size_t)tm.rank * B.W.chunk;
+    lw = B.W.wscr + c0;
+    lv = B.W.wscr + B.M.Lp + c0;
   }
-  BlockTeam tm;
-  for (int s = 0; s < n_steps; ++s)
+  const unsigned long long t0 = wall_clock64();
+  int s = 0;
+  for (; s < n_steps; ++s)
     if (!device_step<T, MODEL>(tm, B, a, cfg, dt, lw, lv, red, yb, flag, X)) break;
-  if (threadIdx.x == 0) {
+  if (tm.rank == 0 && threadIdx.x == 0) {
     tab[id].t = B.t;
     tab[id].step_idx = B.step_idx;
     tab[id].nhist = B.nhist;
     tab[id].hist_new = B.hist_new;
     tab[id].hist_old = B.hist_old;
+    B.W.ctrl->ticks += wall_clock64() - t0;
+    B.W.ctrl->ticked_steps += s;
+  }
+  __syncthreads();                               // B is rewritten for the next instance
+}
+
+template <typename T, int MODEL>
+__global__ __launch_bounds__(kThreads) void k_batch(BatchInst* tab, const BatchWork* work, const int* ids,
+                                                    KrylovCfg cfg, double dt, int n_steps, int lds_slices) {
+  extern __shared__ double lds[];
+  int* flag = (int*)(lds + 32 + kMaxM);
+  // the instance record and the projection arguments: one copy per workgroup in LDS
+  __shared__ BatchInst B;
+  __shared__ ExpvArgs a;
+  const BatchWork wk = work[blockIdx.x];
+  if (wk.G > 1) {
+    // one member of a team (flags and ring emptied by k_prep_batch_teams before the launch)
+    const KWork& W = tab[wk.inst].W;
+    GridTeam tm{wk.G, wk.rank, W.flags, W.ring, &W.ctrl->err, 0ull, 0u, false, 0u, nullptr, 0, 0u};
+    run_instance<T, MODEL>(tm, tab, wk.inst, B, a, cfg, dt, n_steps, lds, lds_slices, flag);
+  } else {
+    for (int q = 0; q < wk.count; ++q) {
+      BlockTeam tm;
+      run_instance<T, MODEL>(tm, tab, ids[wk.first + q], B, a, cfg, dt, n_steps, lds, lds_slices, flag);
+    }
+  }
+}
+
+// Barrier flags to zero and all-reduce rings to empty for every team of the launch (one
+// workgroup per work item; only rank 0's item does the team's).
+__global__ void k_prep_batch_teams(BatchInst* tab, const BatchWork* work) {
+  const BatchWork wk = work[blockIdx.x];
+  if (wk.G <= 1 || wk.rank != 0) return;
+  const KWork& W = tab[wk.inst].W;
+  for (int i = threadIdx.x; i < kRing * wk.G; i += blockDim.x) {
+    if (i < wk.G) W.flags[i] = 0ull;
+    W.ring[i] = kEmpty;
   }
 }
 
@@ -187,9 +225,10 @@ static const void* batch_kernel(int prec, int model) {
   return reinterpret_cast<const void*>(&k_batch<float, kYeoh>);
 }
 
-hipError_t launch_batch(BatchInst* tab, const int* ids, int count, int model, const KrylovCfg& cfg, double dt,
-                        int n_steps, int max_lds_chunk, hipStream_t st) {
-  if (count <= 0) return hipSuccess;
+hipError_t launch_batch(BatchInst* tab, const BatchWork* work, const int* ids, int n_work, bool teams, int model,
+                        const KrylovCfg& cfg, double dt, int n_steps, int max_lds_chunk, hipStream_t st) {
+  if (n_work <= 0) return hipSuccess;
+  if (teams) k_prep_batch_teams<<<n_work, 64, 0, st>>>(tab, work);
   const void* fn = batch_kernel(cfg.prec, model);
   const size_t lds = batch_lds_bytes(max_lds_chunk);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -198,8 +237,16 @@ hipError_t launch_batch(BatchInst* tab, const int* ids, int count, int model, co
   double d = dt;
   int n = n_steps;
   int ls = 2 * max_lds_chunk;
-  void* args[] = {&tab, &ids, &c, &d, &n, &ls};
-  return hipLaunchKernel(fn, dim3(count), dim3(kThreads), args, lds, st);
+  void* args[] = {&tab, &work, &ids, &c, &d, &n, &ls};
+  return hipLaunchKernel(fn, dim3(n_work), dim3(kThreads), args, lds, st);
+}
+
+hipError_t batch_max_blocks(int prec, int model, int max_lds_chunk, int* blocks_per_cu) {
+  const void* fn = batch_kernel(prec, model);
+  const size_t lds = batch_lds_bytes(max_lds_chunk);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, kThreads, lds);
 }
 
 }  // namespace ep

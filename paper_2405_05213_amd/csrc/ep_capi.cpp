@@ -93,8 +93,12 @@ struct ep_ctx {
   size_t o_batch_tab = 0;
   // batch
   std::vector<BatchInst> btab;          // host mirror of the device records
-  std::vector<int> bids[kModels];       // instance ids per material model
+  std::vector<int> bids[kModels];       // instance ids per material model (packed lists of the plan)
   size_t o_bids[kModels] = {};
+  std::vector<BatchWork> bwork[kModels];  // the launch plan: one record per workgroup
+  size_t o_bwork[kModels] = {};
+  size_t bwork_cap = 0;
+  int bteam_max = 1;                    // largest team of the current plan
   int max_lds_chunk = 0;
   hipGraphExec_t bgraph = nullptr;
   hipGraph_t bgraph_src = nullptr;
@@ -296,9 +300,11 @@ static size_t plan_all(ep_ctx* c) {
   if (!c->batch) {
     plan_inst(c, c->one, L, Gmax);
   } else {
-    for (auto& I : c->insts) plan_inst(c, I, L, 1);
+    for (auto& I : c->insts) plan_inst(c, I, L, kBatchGmax);
     c->o_batch_tab = L.take(sizeof(BatchInst) * std::max<size_t>(c->insts.size(), 1));
     for (int k = 0; k < kModels; ++k) c->o_bids[k] = L.take(4 * std::max<size_t>(c->insts.size(), 1));
+    c->bwork_cap = std::max<size_t>(c->insts.size(), 4 * (size_t)std::max(c->cus, 1)) + 1;
+    for (int k = 0; k < kModels; ++k) c->o_bwork[k] = L.take(sizeof(BatchWork) * c->bwork_cap);
   }
   return L.off + kAlign;
 }
@@ -1349,6 +1355,173 @@ ep_status ep_batch_add_instance(ep_ctx* c, int64_t n_nodes, const double* xyz, i
   return EP_OK;
 }
 
+// ------------------------------------------------------------------------- batch plans
+// A plan gives instance i a team of G[i] workgroups (G[i] > 1) or a place in one of the
+// bins (lists of instances that one workgroup steps one after the other).  Applying it sets
+// each instance's slice size and placement, uploads the work records and the bins, and
+// drops the captured step graph.
+static ep_status apply_batch_plan(ep_ctx* c, const std::vector<int>& G, const std::vector<std::vector<int>>& bins) {
+  const int n = (int)c->insts.size();
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  EP_HIP(c, hipMemcpy(c->btab.data(), dptr<BatchInst>(c, c->o_batch_tab), sizeof(BatchInst) * n,
+                      hipMemcpyDeviceToHost));
+  c->max_lds_chunk = 0;
+  c->bteam_max = 1;
+  for (int i = 0; i < n; ++i) {
+    Inst& I = c->insts[i];
+    const int g = std::max(1, std::min(G[i], kBatchGmax));
+    int chunk = (I.Lp + g - 1) / g;
+    chunk = (chunk + 63) / 64 * 64;
+    I.W.G = g;
+    I.W.chunk = chunk;
+    BatchInst& B = c->btab[i];
+    B.W.G = g;
+    B.W.chunk = chunk;
+    B.use_lds = chunk <= kMaxChunk ? 1 : 0;
+    if (B.use_lds) c->max_lds_chunk = std::max(c->max_lds_chunk, chunk);
+    c->bteam_max = std::max(c->bteam_max, g);
+  }
+  for (int k = 0; k < kModels; ++k) {
+    c->bwork[k].clear();
+    c->bids[k].clear();
+  }
+  for (int i = 0; i < n; ++i)
+    if (c->insts[i].W.G > 1) {
+      const int k = c->insts[i].model;
+      for (int r = 0; r < c->insts[i].W.G; ++r) c->bwork[k].push_back(BatchWork{i, r, c->insts[i].W.G, 0, 0});
+    }
+  for (const auto& bin : bins) {
+    // a bin holds instances of one material model (one launch per model)
+    std::vector<int> members[kModels];
+    for (int i : bin)
+      if (c->insts[i].W.G == 1) members[c->insts[i].model].push_back(i);
+    for (int k = 0; k < kModels; ++k) {
+      if (members[k].empty()) continue;
+      c->bwork[k].push_back(BatchWork{-1, 0, 1, (int)c->bids[k].size(), (int)members[k].size()});
+      for (int i : members[k]) c->bids[k].push_back(i);
+    }
+  }
+  for (int k = 0; k < kModels; ++k) {
+    if (c->bwork[k].size() > c->bwork_cap) return fail(c, EP_ERR_ARG, "batch plan has too many workgroups");
+    if (c->bwork[k].empty()) continue;
+    EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_bwork[k]), c->bwork[k].data(), sizeof(BatchWork) * c->bwork[k].size(),
+                        hipMemcpyHostToDevice));
+    EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_bids[k]), c->bids[k].data(), 4 * c->bids[k].size(),
+                        hipMemcpyHostToDevice));
+  }
+  EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_batch_tab), c->btab.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice));
+  if (c->bgraph) { (void)hipGraphExecDestroy(c->bgraph); c->bgraph = nullptr; }
+  if (c->bgraph_src) { (void)hipGraphDestroy(c->bgraph_src); c->bgraph_src = nullptr; }
+  return EP_OK;
+}
+
+// Workgroups of one batch launch that can be resident together (teams wait on each other,
+// so a plan with teams must not exceed it).
+static ep_status batch_capacity(ep_ctx* c, int* cap) {
+  int bpc = 0;
+  int best = 1 << 30;
+  for (int k = 0; k < kModels; ++k) {
+    if (c->bids[k].empty() && c->bwork[k].empty()) continue;
+    // the largest slice the plan may choose keeps the LDS of one workgroup per CU
+    EP_HIP(c, batch_max_blocks(c->cfg.prec, k, kMaxChunk, &bpc));
+    best = std::min(best, std::max(1, bpc) * std::max(1, c->cus));
+  }
+  *cap = best == (1 << 30) ? std::max(1, c->cus) : best;
+  return EP_OK;
+}
+
+// Cost of one step of each instance on one workgroup: the measured wall-clock ticks per step
+// when every instance has them, else elements + Lp / 10 (the element pass dominates).
+static std::vector<double> batch_costs(ep_ctx* c) {
+  const int n = (int)c->insts.size();
+  std::vector<double> cost(n, 0.0);
+  bool measured = true;
+  for (int i = 0; i < n; ++i) {
+    Ctrl h;
+    if (hipMemcpy(&h, c->insts[i].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost) != hipSuccess || h.ticked_steps <= 0) {
+      measured = false;
+      break;
+    }
+    cost[i] = (double)h.ticks / (double)h.ticked_steps;
+  }
+  if (!measured)
+    for (int i = 0; i < n; ++i) cost[i] = (double)c->insts[i].n_elems + 0.1 * (double)c->insts[i].Lp;
+  return cost;
+}
+
+// Smallest makespan plan within `cap` workgroups per launch: instances costlier than the
+// target T get a team of ceil(cost / (T - o)) workgroups (o = overhead * the largest cost:
+// the team's synchronisation), the others are packed first-fit-decreasing into bins of
+// capacity T; T is found by bisection.
+static void make_batch_plan(ep_ctx* c, const std::vector<double>& cost, int cap, double overhead,
+                            std::vector<int>& G, std::vector<std::vector<int>>& bins) {
+  const int n = (int)cost.size();
+  double cmax = 0.0, csum = 0.0;
+  for (double x : cost) { cmax = std::max(cmax, x); csum += x; }
+  const double o = overhead * cmax;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  auto build = [&](double T, std::vector<int>& g, std::vector<std::vector<int>>& b) -> long long {
+    g.assign(n, 1);
+    b.clear();
+    std::vector<double> load;
+    long long used = 0;
+    for (int i : order) {
+      if (cost[i] > T) {
+        const double per = T - o;
+        int need = per > 0.0 ? (int)std::ceil(cost[i] / per) : kBatchGmax + 1;
+        if (need > kBatchGmax) return -1;
+        g[i] = std::max(2, need);
+        used += g[i];
+        continue;
+      }
+      size_t k = 0;
+      while (k < load.size() && load[k] + cost[i] > T) ++k;
+      if (k == load.size()) { load.push_back(0.0); b.emplace_back(); }
+      load[k] += cost[i];
+      b[k].push_back(i);
+    }
+    return used + (long long)b.size();
+  };
+  double lo = std::max(csum / std::max(cap, 1), cmax / kBatchGmax), hi = std::max(cmax, csum);
+  std::vector<int> g;
+  std::vector<std::vector<int>> b;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const long long w = build(mid, g, b);
+    if (w >= 0 && w <= cap) hi = mid; else lo = mid;
+  }
+  build(hi, G, bins);
+}
+
+ep_status ep_batch_plan(ep_ctx* c, int max_workgroups, double overhead) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound || !c->batch) return fail(c, EP_ERR_ORDER, "needs a bound batch context");
+  if (!(overhead >= 0.0) || !(overhead < 1.0)) return fail(c, EP_ERR_ARG, "overhead must be in [0, 1)");
+  int cap = 0;
+  ep_status s = batch_capacity(c, &cap);
+  if (s != EP_OK) return s;
+  if (max_workgroups > 0) cap = std::min(cap, max_workgroups);
+  std::vector<int> G;
+  std::vector<std::vector<int>> bins;
+  make_batch_plan(c, batch_costs(c), cap, overhead, G, bins);
+  return apply_batch_plan(c, G, bins);
+}
+
+ep_status ep_batch_get_plan(ep_ctx* c, int32_t id, int* team, int* workgroups) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound || !c->batch) return fail(c, EP_ERR_ORDER, "needs a bound batch context");
+  if (id >= (int32_t)c->insts.size()) return fail(c, EP_ERR_ARG, "instance id out of range");
+  if (team && id >= 0) *team = c->insts[id].W.G;
+  if (workgroups) {
+    size_t w = 0;
+    for (int k = 0; k < kModels; ++k) w += c->bwork[k].size();
+    *workgroups = (int)w;
+  }
+  return EP_OK;
+}
+
 ep_status ep_batch_bind(ep_ctx* c) {
   const int n = (int)c->insts.size();
   c->btab.assign(n, BatchInst{});
@@ -1356,7 +1529,7 @@ ep_status ep_batch_bind(ep_ctx* c) {
   for (int k = 0; k < kModels; ++k) c->bids[k].clear();
   for (int i = 0; i < n; ++i) {
     Inst& I = c->insts[i];
-    ep_status s = setup_inst(c, I, 1, I.Lp, 1);
+    ep_status s = setup_inst(c, I, 1, I.Lp, kBatchGmax);
     if (s != EP_OK) return fail(c, s, "batch instance " + std::to_string(i) + ": " + c->err);
     BatchInst& B = c->btab[i];
     B.M = I.M;
@@ -1372,11 +1545,11 @@ ep_status ep_batch_bind(ep_ctx* c) {
     c->bids[I.model].push_back(i);
   }
   EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_batch_tab), c->btab.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice));
-  for (int k = 0; k < kModels; ++k)
-    if (!c->bids[k].empty())
-      EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_bids[k]), c->bids[k].data(), 4 * c->bids[k].size(),
-                          hipMemcpyHostToDevice));
-  return EP_OK;
+  // default plan: one workgroup per instance
+  std::vector<int> G(n, 1);
+  std::vector<std::vector<int>> bins;
+  for (int i = 0; i < n; ++i) bins.push_back({i});
+  return apply_batch_plan(c, G, bins);
 }
 
 static ep_status need_batch(ep_ctx* c, int32_t id) {
@@ -1424,9 +1597,12 @@ ep_status ep_batch_set_state(ep_ctx* c, int32_t id, double t, const double* u, c
 
 static ep_status batch_launch_all(ep_ctx* c, double dt, int n_steps, hipStream_t st) {
   for (int k = 0; k < kModels; ++k) {
-    if (c->bids[k].empty()) continue;
-    EP_HIP(c, launch_batch(dptr<BatchInst>(c, c->o_batch_tab), dptr<int>(c, c->o_bids[k]), (int)c->bids[k].size(),
-                           k, c->cfg, dt, n_steps, c->max_lds_chunk, st));
+    if (c->bwork[k].empty()) continue;
+    bool teams = false;
+    for (const auto& w : c->bwork[k]) teams |= w.G > 1;
+    EP_HIP(c, launch_batch(dptr<BatchInst>(c, c->o_batch_tab), dptr<BatchWork>(c, c->o_bwork[k]),
+                           dptr<int>(c, c->o_bids[k]), (int)c->bwork[k].size(), teams, k, c->cfg, dt, n_steps,
+                           c->max_lds_chunk, st));
   }
   return EP_OK;
 }
@@ -1673,6 +1849,115 @@ ep_status ep_batch_load_checkpoint(ep_ctx* c, int32_t id, const void* buf, size_
   B.M.s0 = I.M.s0;
   B.M.s_inv = I.M.s_inv;
   EP_HIP(c, hipMemcpy(dptr<BatchInst>(c, c->o_batch_tab) + id, &B, sizeof(BatchInst), hipMemcpyHostToDevice));
+  return EP_OK;
+}
+
+// Autotuner of the batch plan: times `steps` steps of the plain plan (one workgroup per
+// instance), which also measures each instance's cost per step, then of the plans
+// make_batch_plan builds from those costs for a few team overheads; keeps the fastest.
+// Every timing run starts from the same states (checkpoints) and the states are restored
+// afterwards, so the call leaves the trajectory where it was.
+ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, double* ms_per_step) {
+  if (!c) return EP_ERR_ARG;
+  if (!c->bound || !c->batch) return fail(c, EP_ERR_ORDER, "needs a bound batch context");
+  if (!(dt > 0.0) || !std::isfinite(dt) || steps < 1) return fail(c, EP_ERR_ARG, "need dt > 0 and steps >= 1");
+  const int n = (int)c->insts.size();
+  for (auto& I : c->insts)
+    if (!I.state_set) return fail(c, EP_ERR_ORDER, "every instance needs a state");
+  std::vector<std::vector<char>> img(n);
+  for (int i = 0; i < n; ++i) {
+    img[i].resize(ckpt_bytes(c, c->insts[i]));
+    ep_status s = ep_batch_save_checkpoint(c, i, img[i].data(), img[i].size());
+    if (s != EP_OK) return s;
+  }
+  auto restore = [&]() -> ep_status {
+    for (int i = 0; i < n; ++i) {
+      ep_status s = ep_batch_load_checkpoint(c, i, img[i].data(), img[i].size());
+      if (s != EP_OK) return s;
+    }
+    return EP_OK;
+  };
+  hipEvent_t e0, e1;
+  EP_HIP(c, hipEventCreate(&e0));
+  EP_HIP(c, hipEventCreate(&e1));
+  auto timed = [&](double* ms) -> ep_status {
+    ep_status s = restore();
+    if (s == EP_OK) s = ep_batch_step(c, dt, 1);                 // captures the plan's graph
+    if (s == EP_OK) s = ep_sync(c);
+    if (s != EP_OK) return s;
+    EP_HIP(c, hipEventRecord(e0, c->stream));
+    s = ep_batch_step(c, dt, steps);
+    if (s != EP_OK) return s;
+    EP_HIP(c, hipEventRecord(e1, c->stream));
+    EP_HIP(c, hipEventSynchronize(e1));
+    s = ep_sync(c);
+    if (s != EP_OK) return s;
+    float t = 0.0f;
+    EP_HIP(c, hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / steps;
+    return EP_OK;
+  };
+  ep_status s = EP_OK;
+  std::vector<int> bestG(n, 1), G;
+  std::vector<std::vector<int>> bestBins, bins;
+  for (int i = 0; i < n; ++i) bestBins.push_back({i});
+  double best = 0.0;
+  std::vector<double> cost(n, 0.0);
+  int cap = 0;
+  do {
+    s = apply_batch_plan(c, bestG, bestBins);
+    if (s != EP_OK) break;
+    // costs: ticks of the timed steps of the plain plan
+    std::vector<Ctrl> h0(n), h1(n);
+    s = restore();
+    if (s != EP_OK) break;
+    s = ep_batch_step(c, dt, 1);
+    if (s == EP_OK) s = ep_sync(c);
+    if (s != EP_OK) break;
+    for (int i = 0; i < n; ++i) EP_HIP(c, hipMemcpy(&h0[i], c->insts[i].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    EP_HIP(c, hipEventRecord(e0, c->stream));
+    s = ep_batch_step(c, dt, steps);
+    if (s != EP_OK) break;
+    EP_HIP(c, hipEventRecord(e1, c->stream));
+    EP_HIP(c, hipEventSynchronize(e1));
+    s = ep_sync(c);
+    if (s != EP_OK) break;
+    float t = 0.0f;
+    EP_HIP(c, hipEventElapsedTime(&t, e0, e1));
+    best = (double)t / steps;
+    for (int i = 0; i < n; ++i) {
+      EP_HIP(c, hipMemcpy(&h1[i], c->insts[i].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+      const long long ds = h1[i].ticked_steps - h0[i].ticked_steps;
+      cost[i] = ds > 0 ? (double)(h1[i].ticks - h0[i].ticks) / (double)ds : 1.0;
+    }
+    s = batch_capacity(c, &cap);
+    if (s != EP_OK) break;
+    for (double ov : {0.0, 0.03, 0.08, 0.15}) {
+      make_batch_plan(c, cost, cap, ov, G, bins);
+      s = apply_batch_plan(c, G, bins);
+      if (s != EP_OK) break;
+      double ms = 0.0;
+      s = timed(&ms);
+      if (s != EP_OK) break;
+      if (ms < best) {
+        best = ms;
+        bestG = G;
+        bestBins = bins;
+      }
+    }
+  } while (false);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != EP_OK) return s;
+  s = apply_batch_plan(c, bestG, bestBins);
+  if (s == EP_OK) s = restore();
+  if (s != EP_OK) return s;
+  if (workgroups) {
+    size_t w = 0;
+    for (int k = 0; k < kModels; ++k) w += c->bwork[k].size();
+    *workgroups = (int)w;
+  }
+  if (ms_per_step) *ms_per_step = best;
   return EP_OK;
 }
 

@@ -108,6 +108,8 @@ struct Ctrl {
   int log_pos;
   int pad2;
   double drift;
+  unsigned long long ticks;   // batch: wall-clock ticks of this instance's steps (its team's rank 0)
+  long long ticked_steps;     // steps those ticks cover
 };
 
 struct StepLog {
@@ -154,6 +156,16 @@ struct BatchInst {
   int nhist, hist_new, hist_old;
   int use_lds;                // slice buffers in LDS (1) or in W.wscr (0)
 };
+
+// Work of one workgroup of a batch launch: member `rank` of a team of G > 1 workgroups that
+// steps instance `inst` together, or (G == 1) the `count` instances ids[first ..] stepped one
+// after the other.
+struct BatchWork {
+  int inst, rank, G, first, count;
+};
+
+// Largest team of a batch instance (its barrier flags and all-reduce ring are sized for it).
+constexpr int kBatchGmax = 8;
 
 // One launch of the persistent projection kernel: wbar_out = exp(tau A) wbar_in.
 struct ExpvArgs {

@@ -299,6 +299,8 @@ __global__ void k_reset_ctrl(Ctrl* c, int full) {
         c->ks[k].matvecs = 0;
       }
       c->drift = 0.0;
+      c->ticks = 0ull;
+      c->ticked_steps = 0;
     }
   }
 }

@@ -44,7 +44,8 @@ int energy_vec_blocks(const Mesh& M);
 void launch_energy(const Mesh& M, const double* S, double t, double* pe, double* pv, double* out, hipStream_t st);
 
 size_t batch_lds_bytes(int max_lds_chunk);
-hipError_t launch_batch(BatchInst* tab, const int* ids, int count, int model, const KrylovCfg& cfg, double dt,
-                        int n_steps, int max_lds_chunk, hipStream_t st);
+hipError_t launch_batch(BatchInst* tab, const BatchWork* work, const int* ids, int n_work, bool teams, int model,
+                        const KrylovCfg& cfg, double dt, int n_steps, int max_lds_chunk, hipStream_t st);
+hipError_t batch_max_blocks(int prec, int model, int max_lds_chunk, int* blocks_per_cu);
 
 }  // namespace ep

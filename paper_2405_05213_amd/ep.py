@@ -80,6 +80,9 @@ _SIGS = {
     "ep_batch_get_stats": [_vp, _i32, _P(_i64), _P(C.c_int), _P(C.c_int), _P(_dbl), _P(_i64), _P(C.c_int),
                            _P(C.c_int)],
     "ep_batch_get_energy": [_vp, _i32, _P(_dbl), _P(_dbl), _P(_dbl)],
+    "ep_batch_plan": [_vp, C.c_int, _dbl],
+    "ep_batch_autotune": [_vp, _dbl, C.c_int, _P(C.c_int), _P(_dbl)],
+    "ep_batch_get_plan": [_vp, _i32, _P(C.c_int), _P(C.c_int)],
     "ep_batch_checkpoint_size": [_vp, _i32, _P(C.c_size_t)],
     "ep_batch_save_checkpoint": [_vp, _i32, _vp, C.c_size_t],
     "ep_batch_load_checkpoint": [_vp, _i32, _vp, C.c_size_t],
@@ -369,6 +372,23 @@ class Batch(Context):
         u, v = np.empty(n), np.empty(n)
         self._call("ep_batch_get_state", int(iid), C.byref(t), _ptr(u), _ptr(v))
         return t.value, u, v
+
+    def plan(self, max_workgroups=0, overhead=0.05):
+        """Re-plan the launch: teams for costly instances, lists of cheap ones (ep_batch_plan)."""
+        self._call("ep_batch_plan", int(max_workgroups), float(overhead))
+
+    def autotune(self, dt, steps=5):
+        """Time candidate launch plans and keep the fastest (ep_batch_autotune); the states are
+        restored afterwards.  Returns (workgroups per launch, ms per step)."""
+        w, ms = C.c_int(), C.c_double()
+        self._call("ep_batch_autotune", float(dt), int(steps), C.byref(w), C.byref(ms))
+        return w.value, ms.value
+
+    def plan_of(self, iid):
+        """(team size of instance iid, workgroups per launch) of the current plan."""
+        g, w = C.c_int(), C.c_int()
+        self._call("ep_batch_get_plan", int(iid), C.byref(g), C.byref(w))
+        return g.value, w.value
 
     def save_checkpoint(self, iid) -> bytes:
         """Opaque image of one instance's stepping state (ep_batch_save_checkpoint)."""
