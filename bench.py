@@ -497,15 +497,16 @@ def main():
         "energy_rel_err_max": mixed["energy_rel_err_max"],
         "fp64_same_workload": {k: f64[k] for k in ("dof_matvecs_per_s", "time_steps_per_s", "instance_steps_per_s",
                                                    "ms_per_step", "energy_rel_err_max", "energy_rel_err_median",
-                                                   "matvecs_per_step", "m_corr_range", "m_pred_range")},
+                                                   "matvecs_per_step", "m_corr_range", "m_pred_range", "plan")},
         "mixed_vs_fp64": {"time_steps_per_s": mixed["time_steps_per_s"] / f64["time_steps_per_s"],
                           "dof_matvecs_per_s": mixed["dof_matvecs_per_s"] / f64["dof_matvecs_per_s"],
                           "energy_gate_1e-6_met_by_both": gate},
         "headline_detail": {k: mixed[k] for k in ("energy_rel_err_median", "matvecs_per_step", "m_corr_range",
-                                                  "m_pred_range")},
+                                                  "m_pred_range", "plan")},
         "roofline": {
-            "kernel": "k_batch<float, 1> (one workgroup per instance: operator applies, Arnoldi-MGS, exponential, "
-                      "predictor and corrector of one time step), one launch per step",
+            "kernel": "k_batch<float, 1> (workgroups stepping lists of instances or teams of workgroups stepping one "
+                      "instance: operator applies, Arnoldi-MGS, exponential, predictor and corrector of one time "
+                      "step), one launch per step",
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(workload, "mixed_f32"),
             "alg_bytes_per_launch": mixed["alg_bytes_per_launch"], "avg_launch_ms": launch_s * 1e3,

@@ -49,11 +49,11 @@ def counters(db: str, top: int = 15):
 
 
 # the sources that define the persistent projection kernel (the .hip files only instantiate it)
-PROJECTION_KERNEL_SOURCES = ("ep_common.hpp", "ep_device.hpp", "ep_expm.hpp", "ep_tangent.hpp", "ep_krylov.hpp",
-                             "ep_expv.hpp")
+PROJECTION_KERNEL_SOURCES = ("ep_common.hpp", "ep_device.hpp", "ep_expm.hpp", "ep_tangent.hpp", "ep_q2.hpp",
+                             "ep_krylov.hpp", "ep_expv.hpp")
 
 
-# ... and those of the batch kernel (one workgroup per instance)
+# ... and those of the batch kernel (lists of instances or teams per workgroup)
 BATCH_KERNEL_SOURCES = PROJECTION_KERNEL_SOURCES + ("ep_batch.hip",)
 
 
