@@ -147,15 +147,17 @@ __device__ void run_instance(Team& tm, BatchInst* tab, int id, BatchInst& B, Exp
     B = tab[id];
   }
   __syncthreads();
+  // slices: both in LDS (use_lds 1), w's in LDS and the newest basis vector read back from V
+  // (2), or w's in device memory and the basis vector from V (0)
   double* lw;
-  double* lv;
-  if (B.use_lds) {
+  double* lv = nullptr;
+  if (B.use_lds == 1) {
     lw = lds + kBatchHead;
     lv = lw + B.W.chunk;
+  } else if (B.use_lds == 2) {
+    lw = lds + kBatchHead;
   } else {
-    const size_t c0 = (size_t)tm.rank * B.W.chunk;
-    lw = B.W.wscr + c0;
-    lv = B.W.wscr + B.M.Lp + c0;
+    lw = B.W.wscr + (size_t)tm.rank * B.W.chunk;
   }
   const unsigned long long t0 = wall_clock64();
   int s = 0;

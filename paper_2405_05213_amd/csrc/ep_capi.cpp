@@ -1377,8 +1377,9 @@ static ep_status apply_batch_plan(ep_ctx* c, const std::vector<int>& G, const st
     BatchInst& B = c->btab[i];
     B.W.G = g;
     B.W.chunk = chunk;
-    B.use_lds = chunk <= kMaxChunk ? 1 : 0;
-    if (B.use_lds) c->max_lds_chunk = std::max(c->max_lds_chunk, chunk);
+    B.use_lds = chunk <= kMaxChunk ? 1 : (chunk <= 2 * kMaxChunk ? 2 : 0);
+    if (B.use_lds == 1) c->max_lds_chunk = std::max(c->max_lds_chunk, chunk);
+    if (B.use_lds == 2) c->max_lds_chunk = std::max(c->max_lds_chunk, (chunk + 1) / 2);
     c->bteam_max = std::max(c->bteam_max, g);
   }
   for (int k = 0; k < kModels; ++k) {
@@ -1540,8 +1541,7 @@ ep_status ep_batch_bind(ep_ctx* c) {
     B.step_idx = 0;
     B.nhist = 0;
     B.hist_new = B.hist_old = -1;
-    B.use_lds = I.Lp <= kMaxChunk ? 1 : 0;
-    if (B.use_lds) c->max_lds_chunk = std::max(c->max_lds_chunk, I.Lp);
+    B.use_lds = 0;                               // set by the plan
     c->bids[I.model].push_back(i);
   }
   EP_HIP(c, hipMemcpy(dptr<char>(c, c->o_batch_tab), c->btab.data(), sizeof(BatchInst) * n, hipMemcpyHostToDevice));

@@ -154,7 +154,8 @@ struct BatchInst {
   double t;
   long long step_idx;
   int nhist, hist_new, hist_old;
-  int use_lds;                // slice buffers in LDS (1) or in W.wscr (0)
+  int use_lds;                // slices of w and the newest basis vector in LDS (1), w's only (2:
+                              // the basis vector is read from V), or w's in W.wscr (0)
 };
 
 // Work of one workgroup of a batch launch: member `rank` of a team of G > 1 workgroups that

@@ -253,6 +253,9 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
   double hinv = 1.0 / beta;
   const double* src = W.X;
+  // lv == nullptr: only w's slice is held (LDS too small for two); the newest basis vector
+  // is read back from its row of V where the held copy would be used
+  const bool lvV = lv == nullptr;
   for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
     double x[kLB];
 #pragma unroll
@@ -310,7 +313,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
         const int i = i0 + u * blockDim.x;
         if (i < nloc) {
           lw[i] = w[u];
-          lv[i] = v0[u];
+          if (!lvV) lv[i] = v0[u];
           part += w[u] * v0[u];
         }
       }
@@ -318,7 +321,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     // the next basis slice is loaded while each reduction is in flight
     // prefetch only in the linear kernels (reduction-latency bound); the secant-material
     // kernels need those registers for their element code
-    const bool pf_ok = (MODEL == kLinear || MODEL == kStored) && nloc <= kPF * (int)blockDim.x;
+    const bool pf_ok = (MODEL == kLinear || MODEL == kStored) && nloc <= kPF * (int)blockDim.x && !lvV;
     double pf[kPF];
     double hp = tm.post(part, red, flag, false);
     if (pf_ok && 1 < j) prefetch_row(pf, W.V + Lp + c0, nloc);
@@ -345,6 +348,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
           }
         } else {
           const double* Vi = W.V + (size_t)i * Lp + c0;
+          const double* Vp = lvV ? Vi - Lp : lv;         // v_{i-1}
           for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
             double a[kLB], b[kLB], q[kLB];
 #pragma unroll
@@ -352,7 +356,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
               const int t = t0 + u * blockDim.x;
               if (t < nloc) {
                 a[u] = lw[t];
-                b[u] = lv[t];
+                b[u] = Vp[t];
                 q[u] = Vi[t];
               }
             }
@@ -362,7 +366,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
               if (t < nloc) {
                 const double w = a[u] - hprev * b[u];
                 lw[t] = w;
-                lv[t] = q[u];
+                if (!lvV) lv[t] = q[u];
                 part += w * q[u];
               }
             }
@@ -377,6 +381,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
         finite &= fabs(h) < INFINITY;
         hprev = h;
       } else {
+        const double* Vp = lvV ? W.V + (size_t)(j - 1) * Lp + c0 : lv;   // v_{j-1}
         for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
           double a[kLB], b[kLB];
 #pragma unroll
@@ -384,7 +389,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
             const int t = t0 + u * blockDim.x;
             if (t < nloc) {
               a[u] = lw[t];
-              b[u] = lv[t];
+              b[u] = Vp[t];
             }
           }
 #pragma unroll
