@@ -58,10 +58,14 @@ struct KLds {
 // the kernel's register allocation into spills.
 constexpr int kPF = 4;
 
-// Entries per thread whose loads a slice loop issues before their stores.  The slices may
-// sit in LDS or in device memory behind one generic pointer, so a store can alias any later
-// load and would otherwise hold back the next entry's loads for a full memory round trip.
-constexpr int kLB = 4;
+// Entries per thread whose loads a slice loop issues before their stores (template parameter
+// LB of the projections).  The slices may sit in LDS or in device memory behind one generic
+// pointer, so a store can alias any later load and would otherwise hold back the next entry's
+// loads for a full memory round trip.  Worth it where a thread owns many entries (a batch
+// instance on one workgroup: 8.63 -> 7.31 ms per rubber-batch step); a cost where it owns about
+// one (the single-instance team: c2 6.43 -> 6.54 ms), so the batch kernel uses 4, the team
+// kernel 1.
+constexpr int kLBBatch = 4;
 
 __device__ __forceinline__ void prefetch_row(double (&pf)[kPF], const double* row, int nloc) {
 #pragma unroll
@@ -230,7 +234,7 @@ __device__ __forceinline__ int check_point(Team& tm, const ExpvArgs& A, int j, d
 
 // X <- exp(f A) X on entry ||X|| = beta (SCH = 4: exp(f Omega) X).  Every workgroup returns
 // the same result.
-template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8>
+template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8, int LB = 1>
 __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
                               double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
@@ -256,15 +260,15 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
   // lv == nullptr: only w's slice is held (LDS too small for two); the newest basis vector
   // is read back from its row of V where the held copy would be used
   const bool lvV = lv == nullptr;
-  for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
-    double x[kLB];
+  for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
+    double x[LB];
 #pragma unroll
-    for (int u = 0; u < kLB; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int i = i0 + u * blockDim.x;
       x[u] = i < nloc ? W.X[c0 + i] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < kLB; ++u) {
+    for (int u = 0; u < LB; ++u) {
       const int i = i0 + u * blockDim.x;
       if (i < nloc) W.V[c0 + i] = x[u] * hinv;
     }
@@ -287,10 +291,10 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     const double xs = src[2 * n3] * hinv * M.s_inv;      // s-entry of v_{j-1} / s0
     const SlotMap sm = slot_map(M);                       // not held across the element pass
     double part = 0.0;
-    for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
-      double w[kLB], v0[kLB];
+    for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
+      double w[LB], v0[LB];
 #pragma unroll
-      for (int u = 0; u < kLB; ++u) {
+      for (int u = 0; u < LB; ++u) {
         const int i = i0 + u * blockDim.x;
         w[u] = 0.0;
         v0[u] = 0.0;
@@ -309,7 +313,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
         }
       }
 #pragma unroll
-      for (int u = 0; u < kLB; ++u) {
+      for (int u = 0; u < LB; ++u) {
         const int i = i0 + u * blockDim.x;
         if (i < nloc) {
           lw[i] = w[u];
@@ -349,10 +353,10 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
         } else {
           const double* Vi = W.V + (size_t)i * Lp + c0;
           const double* Vp = lvV ? Vi - Lp : lv;         // v_{i-1}
-          for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
-            double a[kLB], b[kLB], q[kLB];
+          for (int t0 = threadIdx.x; t0 < nloc; t0 += LB * blockDim.x) {
+            double a[LB], b[LB], q[LB];
 #pragma unroll
-            for (int u = 0; u < kLB; ++u) {
+            for (int u = 0; u < LB; ++u) {
               const int t = t0 + u * blockDim.x;
               if (t < nloc) {
                 a[u] = lw[t];
@@ -361,7 +365,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
               }
             }
 #pragma unroll
-            for (int u = 0; u < kLB; ++u) {
+            for (int u = 0; u < LB; ++u) {
               const int t = t0 + u * blockDim.x;
               if (t < nloc) {
                 const double w = a[u] - hprev * b[u];
@@ -382,10 +386,10 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
         hprev = h;
       } else {
         const double* Vp = lvV ? W.V + (size_t)(j - 1) * Lp + c0 : lv;   // v_{j-1}
-        for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
-          double a[kLB], b[kLB];
+        for (int t0 = threadIdx.x; t0 < nloc; t0 += LB * blockDim.x) {
+          double a[LB], b[LB];
 #pragma unroll
-          for (int u = 0; u < kLB; ++u) {
+          for (int u = 0; u < LB; ++u) {
             const int t = t0 + u * blockDim.x;
             if (t < nloc) {
               a[u] = lw[t];
@@ -393,7 +397,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
             }
           }
 #pragma unroll
-          for (int u = 0; u < kLB; ++u) {
+          for (int u = 0; u < LB; ++u) {
             const int t = t0 + u * blockDim.x;
             if (t < nloc) {
               const double w = a[u] - hprev * b[u];
@@ -416,15 +420,15 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     if (!breakdown) {
       hinv = 1.0 / hn;
       double* Vj = W.V + (size_t)j * Lp + c0;
-      for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
-        double a[kLB];
+      for (int t0 = threadIdx.x; t0 < nloc; t0 += LB * blockDim.x) {
+        double a[LB];
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
+        for (int u = 0; u < LB; ++u) {
           const int t = t0 + u * blockDim.x;
           a[u] = t < nloc ? lw[t] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
+        for (int u = 0; u < LB; ++u) {
           const int t = t0 + u * blockDim.x;
           if (t < nloc) Vj[t] = a[u] * hinv;
         }
@@ -445,7 +449,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
 // Compact-WY form of the projection (see the file header).  Per step: the operator barrier,
 // one vector all-reduce of the 2j - 1 inner products, the fenced norm all-reduce.
-template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8>
+template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8, int LB = 1>
 __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
                                   double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
@@ -490,10 +494,10 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     // w = f A v_{j-1} on the own slice
     const double xs = src[2 * n3] * hinv * M.s_inv;
     const SlotMap sm = slot_map(M);
-    for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
-      double w[kLB];
+    for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
+      double w[LB];
 #pragma unroll
-      for (int u = 0; u < kLB; ++u) {
+      for (int u = 0; u < LB; ++u) {
         const int i = i0 + u * blockDim.x;
         w[u] = 0.0;
         if (i < nloc) {
@@ -510,7 +514,7 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
         }
       }
 #pragma unroll
-      for (int u = 0; u < kLB; ++u) {
+      for (int u = 0; u < LB; ++u) {
         const int i = i0 + u * blockDim.x;
         if (i < nloc) lw[i] = w[u];
       }
@@ -631,15 +635,15 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     if (!breakdown) {
       hinv = 1.0 / hn;
       double* Vj = W.V + (size_t)j * Lp + c0;
-      for (int t0 = threadIdx.x; t0 < nloc; t0 += kLB * blockDim.x) {
-        double a[kLB];
+      for (int t0 = threadIdx.x; t0 < nloc; t0 += LB * blockDim.x) {
+        double a[LB];
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
+        for (int u = 0; u < LB; ++u) {
           const int t = t0 + u * blockDim.x;
           a[u] = t < nloc ? lw[t] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < kLB; ++u) {
+        for (int u = 0; u < LB; ++u) {
           const int t = t0 + u * blockDim.x;
           if (t < nloc) {
             const double v = a[u] * hinv;
@@ -669,7 +673,7 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
 
 // wbar_out = exp(tau A) wbar_in with the sticky substep count and subspace-size hint of
 // this projection kind; writes statistics and sticky errors.
-template <typename T, int MODEL, class Team, int ORTHO = 0, int SCH = 2, int NPE = 8>
+template <typename T, int MODEL, class Team, int ORTHO = 0, int SCH = 2, int NPE = 8, int LB = 1>
 __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, double* red, double* yb,
                           int* flag, const KLds& cx) {
   const Mesh& M = A.M;
@@ -687,15 +691,15 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
   double last_eps = 0.0;
   for (;;) {
     double part = 0.0;
-    for (int i0 = threadIdx.x; i0 < nloc; i0 += kLB * blockDim.x) {
-      double x[kLB];
+    for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
+      double x[LB];
 #pragma unroll
-      for (int u = 0; u < kLB; ++u) {
+      for (int u = 0; u < LB; ++u) {
         const int i = i0 + u * blockDim.x;
         x[u] = i < nloc ? A.x_in[c0 + i] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < kLB; ++u) {
+      for (int u = 0; u < LB; ++u) {
         const int i = i0 + u * blockDim.x;
         if (i < nloc) {
           W.X[c0 + i] = x[u];
@@ -710,9 +714,9 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
     for (int sub = 0; sub < k; ++sub) {
       ProjResult r;
       if constexpr (Team::kVecReduce && ORTHO == 1)
-        r = project_cwy<T, MODEL, Team, SCH, NPE>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+        r = project_cwy<T, MODEL, Team, SCH, NPE, LB>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       else
-        r = project<T, MODEL, Team, SCH, NPE>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+        r = project<T, MODEL, Team, SCH, NPE, LB>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       if (tm.dead) return;
       nmv += r.nmv;
       if (r.status != 0) { status = r.status; ok = false; break; }
