@@ -368,25 +368,33 @@ ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs,
  * its reductions through device memory with bounded waits: a team whose members are not
  * all resident records EP_ERR_DEVICE instead of hanging).  The step lasts as long as its
  * longest workgroup.
- * At binding every instance has a workgroup of its own.  ep_batch_plan re-plans: instances
- * whose cost per step exceeds a target T get a team of ceil(cost / (T - overhead * the
- * largest cost)) workgroups, the others are packed first-fit-decreasing into lists of cost
- * <= T, and T is the smallest target whose plan needs at most max_workgroups workgroups
- * (<= 0: as many as can be resident together on this GPU) per launch.  The cost of an
- * instance is its measured wall-clock time per step when every instance has stepped since
- * its state was set, else its element count plus a tenth of its Krylov-vector length.
- * overhead in [0, 1).  Results of an instance depend on its team size at rounding level
- * (reductions in another order).
+ * At binding every instance has a workgroup of its own.  ep_batch_plan re-plans, modelling a
+ * team of G workgroups to step an instance of cost c in c (serial + (1 - serial) / G) (serial
+ * in [0, 1): the part of a step a team does not divide - synchronisation, check points):
+ * instances whose cost exceeds a target T get the smallest team that meets it, the others
+ * are packed first-fit-decreasing into lists of cost <= T, and T is the smallest target whose
+ * plan needs at most max_workgroups workgroups (<= 0: as many as can be resident together on
+ * this GPU) per launch.  The cost of an instance is its measured wall-clock time per step
+ * when every instance has stepped since its state was set, else its element count plus a
+ * tenth of its Krylov-vector length.  Results of an instance depend on its team size at
+ * rounding level (reductions in another order).
  * ep_batch_autotune times `steps` steps of dt (after one untimed step) for the one-
- * workgroup-per-instance plan, which measures the costs, and for the plans of overheads
- * 0, 0.03, 0.08 and 0.15, each from the same states, keeps the fastest and restores the
- * states (checkpoints), so the trajectory is where it was; outputs the workgroups per
- * launch and the time per step of the kept plan (either may be NULL).
+ * workgroup-per-instance plan, which measures the costs, and for the plans of serial
+ * fractions 0.2, 0.35, 0.5 and 0.65; then re-measures the costs under the fastest plan so far
+ * (team times converted back through the model) and times the four plans of those costs;
+ * each run starts from the same states.  Keeps the fastest plan and restores the states
+ * (checkpoints), so the trajectory is where it was; outputs the workgroups per launch and
+ * the time per step of the kept plan (either may be NULL).
  * ep_batch_get_plan: the team size of instance instance_id (1: a list member) and the total
  * workgroups of the current plan (either may be NULL; instance_id < 0 skips the first). */
-ep_status ep_batch_plan(ep_ctx* ctx, int max_workgroups, double overhead);
+ep_status ep_batch_plan(ep_ctx* ctx, int max_workgroups, double serial);
 ep_status ep_batch_autotune(ep_ctx* ctx, double dt, int steps, int* workgroups, double* ms_per_step);
 ep_status ep_batch_get_plan(ep_ctx* ctx, int32_t instance_id, int* team, int* workgroups);
+/* Device wall-clock time per step of one instance (its workgroup's, or its team's first
+ * member's, time from the start of its first step in a launch to the end of its last),
+ * averaged over the steps since its state was set (synchronising; either output may be
+ * NULL).  The plan's costs; a list's members run one after the other. */
+ep_status ep_batch_get_time(ep_ctx* ctx, int32_t instance_id, double* us_per_step, int64_t* steps);
 /* Checkpoints of one instance, as ep_checkpoint_size / ep_save_checkpoint /
  * ep_load_checkpoint (the save synchronises and returns that instance's failure only; a
  * load needs a batch instance of the same sizes, material, precision). */

@@ -1450,16 +1450,16 @@ static std::vector<double> batch_costs(ep_ctx* c) {
   return cost;
 }
 
-// Smallest makespan plan within `cap` workgroups per launch: instances costlier than the
-// target T get a team of ceil(cost / (T - o)) workgroups (o = overhead * the largest cost:
-// the team's synchronisation), the others are packed first-fit-decreasing into bins of
-// capacity T; T is found by bisection.
-static void make_batch_plan(ep_ctx* c, const std::vector<double>& cost, int cap, double overhead,
+// Smallest makespan plan within `cap` workgroups per launch.  A team of G workgroups is
+// modelled to step an instance of cost c in c (a + (1 - a) / G), a the part of a step that a
+// team does not divide (its synchronisations, the check points, latency-bound phases);
+// instances costlier than the target T get the smallest team that meets it, the others are
+// packed first-fit-decreasing into lists of cost <= T; T is found by bisection.
+static void make_batch_plan(ep_ctx* c, const std::vector<double>& cost, int cap, double serial,
                             std::vector<int>& G, std::vector<std::vector<int>>& bins) {
   const int n = (int)cost.size();
   double cmax = 0.0, csum = 0.0;
   for (double x : cost) { cmax = std::max(cmax, x); csum += x; }
-  const double o = overhead * cmax;
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
   std::sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -1470,11 +1470,12 @@ static void make_batch_plan(ep_ctx* c, const std::vector<double>& cost, int cap,
     long long used = 0;
     for (int i : order) {
       if (cost[i] > T) {
-        const double per = T - o;
-        int need = per > 0.0 ? (int)std::ceil(cost[i] / per) : kBatchGmax + 1;
-        if (need > kBatchGmax) return -1;
-        g[i] = std::max(2, need);
-        used += g[i];
+        int need = 0;
+        for (int q = 2; q <= kBatchGmax && !need; ++q)
+          if (cost[i] * (serial + (1.0 - serial) / q) <= T) need = q;
+        if (!need) return -1;
+        g[i] = need;
+        used += need;
         continue;
       }
       size_t k = 0;
@@ -1485,7 +1486,8 @@ static void make_batch_plan(ep_ctx* c, const std::vector<double>& cost, int cap,
     }
     return used + (long long)b.size();
   };
-  double lo = std::max(csum / std::max(cap, 1), cmax / kBatchGmax), hi = std::max(cmax, csum);
+  double lo = std::max(csum / std::max(cap, 1), cmax * (serial + (1.0 - serial) / kBatchGmax)),
+         hi = std::max(cmax, csum);
   std::vector<int> g;
   std::vector<std::vector<int>> b;
   for (int it = 0; it < 60; ++it) {
@@ -1496,17 +1498,17 @@ static void make_batch_plan(ep_ctx* c, const std::vector<double>& cost, int cap,
   build(hi, G, bins);
 }
 
-ep_status ep_batch_plan(ep_ctx* c, int max_workgroups, double overhead) {
+ep_status ep_batch_plan(ep_ctx* c, int max_workgroups, double serial) {
   if (!c) return EP_ERR_ARG;
   if (!c->bound || !c->batch) return fail(c, EP_ERR_ORDER, "needs a bound batch context");
-  if (!(overhead >= 0.0) || !(overhead < 1.0)) return fail(c, EP_ERR_ARG, "overhead must be in [0, 1)");
+  if (!(serial >= 0.0) || !(serial < 1.0)) return fail(c, EP_ERR_ARG, "serial fraction must be in [0, 1)");
   int cap = 0;
   ep_status s = batch_capacity(c, &cap);
   if (s != EP_OK) return s;
   if (max_workgroups > 0) cap = std::min(cap, max_workgroups);
   std::vector<int> G;
   std::vector<std::vector<int>> bins;
-  make_batch_plan(c, batch_costs(c), cap, overhead, G, bins);
+  make_batch_plan(c, batch_costs(c), cap, serial, G, bins);
   return apply_batch_plan(c, G, bins);
 }
 
@@ -1854,7 +1856,7 @@ ep_status ep_batch_load_checkpoint(ep_ctx* c, int32_t id, const void* buf, size_
 
 // Autotuner of the batch plan: times `steps` steps of the plain plan (one workgroup per
 // instance), which also measures each instance's cost per step, then of the plans
-// make_batch_plan builds from those costs for a few team overheads; keeps the fastest.
+// make_batch_plan builds from those costs for a few serial fractions; keeps the fastest.
 // Every timing run starts from the same states (checkpoints) and the states are restored
 // afterwards, so the call leaves the trajectory where it was.
 ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, double* ms_per_step) {
@@ -1932,17 +1934,44 @@ ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, do
     }
     s = batch_capacity(c, &cap);
     if (s != EP_OK) break;
-    for (double ov : {0.0, 0.03, 0.08, 0.15}) {
-      make_batch_plan(c, cost, cap, ov, G, bins);
-      s = apply_batch_plan(c, G, bins);
-      if (s != EP_OK) break;
-      double ms = 0.0;
-      s = timed(&ms);
-      if (s != EP_OK) break;
-      if (ms < best) {
-        best = ms;
-        bestG = G;
-        bestBins = bins;
+    // two rounds: the plans of the plain plan's costs, then of the costs measured under the
+    // best of them (a fuller machine slows every instance down; a team's time is converted
+    // back to one workgroup's through the same model)
+    double best_sf = -1.0;
+    for (int round = 0; round < 2 && s == EP_OK; ++round) {
+      if (round == 1) {
+        if (best_sf < 0.0) break;
+        s = apply_batch_plan(c, bestG, bestBins);
+        if (s != EP_OK) break;
+        s = restore();
+        if (s == EP_OK) s = ep_batch_step(c, dt, 1);
+        if (s == EP_OK) s = ep_sync(c);
+        if (s != EP_OK) break;
+        for (int i = 0; i < n; ++i) EP_HIP(c, hipMemcpy(&h0[i], c->insts[i].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        s = ep_batch_step(c, dt, steps);
+        if (s == EP_OK) s = ep_sync(c);
+        if (s != EP_OK) break;
+        for (int i = 0; i < n; ++i) {
+          EP_HIP(c, hipMemcpy(&h1[i], c->insts[i].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+          const long long ds = h1[i].ticked_steps - h0[i].ticked_steps;
+          const double t = ds > 0 ? (double)(h1[i].ticks - h0[i].ticks) / (double)ds : cost[i];
+          const int g = c->insts[i].W.G;
+          cost[i] = t / (best_sf + (1.0 - best_sf) / g);
+        }
+      }
+      for (double sf : {0.2, 0.35, 0.5, 0.65}) {
+        make_batch_plan(c, cost, cap, sf, G, bins);
+        s = apply_batch_plan(c, G, bins);
+        if (s != EP_OK) break;
+        double ms = 0.0;
+        s = timed(&ms);
+        if (s != EP_OK) break;
+        if (ms < best) {
+          best = ms;
+          bestG = G;
+          bestBins = bins;
+          best_sf = sf;
+        }
       }
     }
   } while (false);
@@ -1958,6 +1987,19 @@ ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, do
     *workgroups = (int)w;
   }
   if (ms_per_step) *ms_per_step = best;
+  return EP_OK;
+}
+
+ep_status ep_batch_get_time(ep_ctx* c, int32_t id, double* us_per_step, int64_t* steps) {
+  ep_status s = need_batch(c, id);
+  if (s != EP_OK) return s;
+  EP_HIP(c, hipStreamSynchronize(c->stream));
+  Ctrl h;
+  EP_HIP(c, hipMemcpy(&h, c->insts[id].W.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+  int khz = 0;
+  EP_HIP(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+  if (us_per_step) *us_per_step = (h.ticked_steps > 0 && khz > 0) ? 1e3 * (double)h.ticks / khz / h.ticked_steps : 0.0;
+  if (steps) *steps = h.ticked_steps;
   return EP_OK;
 }
 

@@ -83,6 +83,7 @@ _SIGS = {
     "ep_batch_plan": [_vp, C.c_int, _dbl],
     "ep_batch_autotune": [_vp, _dbl, C.c_int, _P(C.c_int), _P(_dbl)],
     "ep_batch_get_plan": [_vp, _i32, _P(C.c_int), _P(C.c_int)],
+    "ep_batch_get_time": [_vp, _i32, _P(_dbl), _P(_i64)],
     "ep_batch_checkpoint_size": [_vp, _i32, _P(C.c_size_t)],
     "ep_batch_save_checkpoint": [_vp, _i32, _vp, C.c_size_t],
     "ep_batch_load_checkpoint": [_vp, _i32, _vp, C.c_size_t],
@@ -373,9 +374,9 @@ class Batch(Context):
         self._call("ep_batch_get_state", int(iid), C.byref(t), _ptr(u), _ptr(v))
         return t.value, u, v
 
-    def plan(self, max_workgroups=0, overhead=0.05):
+    def plan(self, max_workgroups=0, serial=0.35):
         """Re-plan the launch: teams for costly instances, lists of cheap ones (ep_batch_plan)."""
-        self._call("ep_batch_plan", int(max_workgroups), float(overhead))
+        self._call("ep_batch_plan", int(max_workgroups), float(serial))
 
     def autotune(self, dt, steps=5):
         """Time candidate launch plans and keep the fastest (ep_batch_autotune); the states are
@@ -389,6 +390,12 @@ class Batch(Context):
         g, w = C.c_int(), C.c_int()
         self._call("ep_batch_get_plan", int(iid), C.byref(g), C.byref(w))
         return g.value, w.value
+
+    def time_of(self, iid):
+        """(device microseconds per step, steps timed) of instance iid (ep_batch_get_time)."""
+        us, n = C.c_double(), C.c_int64()
+        self._call("ep_batch_get_time", int(iid), C.byref(us), C.byref(n))
+        return us.value, n.value
 
     def save_checkpoint(self, iid) -> bytes:
         """Opaque image of one instance's stepping state (ep_batch_save_checkpoint)."""

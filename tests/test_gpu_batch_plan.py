@@ -48,7 +48,7 @@ def test_teams_match_the_oracle(prec, tol):
     probs = _probs()
     dt = probs[0].dt
     b = batch_from_problems(probs, m_max=32, precision=prec)
-    b.plan(max_workgroups=0, overhead=0.0)          # room for teams: the costly instances get them
+    b.plan(max_workgroups=0, serial=0.0)            # room for teams: the costly instances get them
     teams = [b.plan_of(i)[0] for i in range(len(probs))]
     say(f"[batch plan] teams {teams}, {b.plan_of(0)[1]} workgroups, {prec}")
     assert max(teams) > 1
@@ -78,7 +78,7 @@ def test_mixed_plan_and_autotune_leave_the_states_and_match_the_oracle():
     for (t0, u0, v0), (t1, u1, v1) in zip(before, _states(b, len(probs))):
         assert t0 == t1 and np.array_equal(u0, u1) and np.array_equal(v0, v1)
     # lists and teams in one launch: at most four workgroups per launch for five instances
-    b.plan(max_workgroups=4, overhead=0.0)
+    b.plan(max_workgroups=4, serial=0.0)
     teams = [b.plan_of(i)[0] for i in range(len(probs))]
     assert b.plan_of(0)[1] <= 4 * len({p.model for p in probs})
     b.step(dt, 4)
