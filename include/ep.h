@@ -384,7 +384,9 @@ ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs,
  * (team times converted back through the model) and times the four plans of those costs;
  * each run starts from the same states.  Keeps the fastest plan and restores the states
  * (checkpoints), so the trajectory is where it was; outputs the workgroups per launch and
- * the time per step of the kept plan (either may be NULL).
+ * the time per step of the kept plan (either may be NULL).  On a failure (a device error in
+ * a timing run) it returns that error after putting back one workgroup per instance and
+ * the saved states.
  * ep_batch_get_plan: the team size of instance instance_id (1: a list member) and the total
  * workgroups of the current plan (either may be NULL; instance_id < 0 skips the first). */
 ep_status ep_batch_plan(ep_ctx* ctx, int max_workgroups, double serial);

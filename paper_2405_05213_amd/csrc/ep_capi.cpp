@@ -1977,7 +1977,17 @@ ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, do
   } while (false);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (s != EP_OK) return s;
+  if (s != EP_OK) {
+    // leave the batch as it was found: one workgroup per instance, the saved states (the
+    // error stays the call's result)
+    const std::string why = c->err;
+    std::vector<int> g1(n, 1);
+    std::vector<std::vector<int>> b1;
+    for (int i = 0; i < n; ++i) b1.push_back({i});
+    if (apply_batch_plan(c, g1, b1) == EP_OK) (void)restore();
+    c->err = why;
+    return s;
+  }
   s = apply_batch_plan(c, bestG, bestBins);
   if (s == EP_OK) s = restore();
   if (s != EP_OK) return s;

@@ -96,3 +96,33 @@ def test_batch_failure_stays_with_its_instance():
     orc = Propagator(q, **kw)
     orc.run(q.dt, n)
     assert maxrel(ub, orc.u()) < 1e-8 and maxrel(vb, orc.v()) < 1e-8
+
+
+def test_batch_autotune_failure_puts_the_batch_back():
+    """The plan autotuner meets a device error in its first timing run (an instance whose
+    state inverts elements): it returns that error with one workgroup per instance and the
+    states it started from, and the batch steps on normally once that instance is reset."""
+    epmod = _ep()
+    from paper_2405_05213_amd import batch_from_problems
+    from workloads import batch_instances
+    say("[errors] batch autotune failure")
+    probs = batch_instances(n_inst=3, seed=5, dt=2e-4, nx_range=(4, 8), nyz_range=(2, 3))
+    b = batch_from_problems(probs, m_max=40)
+    bad = 1
+    q = probs[bad]
+    x = q.xyz[:, 0]
+    u = np.zeros(3 * q.n_nodes)
+    u[3 * np.where(x == x.max())[0]] = -3.0 * (x.max() - x.min()) / 4
+    b.set_state(bad, 0.0, u, np.zeros_like(u))
+    before = [b.get_state(i) for i in range(3)]
+    with pytest.raises(epmod.EPError) as e:
+        b.autotune(q.dt, steps=2)
+    assert e.value.code == epmod.EP_ERR_INVERTED
+    assert all(b.plan_of(i)[0] == 1 for i in range(3)) and b.plan_of(0)[1] == 3
+    for (t0, u0, v0), (t1, u1, v1) in zip(before, [b.get_state(i) for i in range(3)]):
+        assert t0 == t1 and np.array_equal(u0, u1) and np.array_equal(v0, v1)
+    b.set_state(bad, 0.0, q.u0, q.v0)
+    b.step(q.dt, 2)
+    for i in range(3):
+        assert b.get_state(i)[0] == pytest.approx(2 * q.dt)
+    b.close()
