@@ -174,8 +174,7 @@ ep_status ep_set_scheme(ep_ctx* ctx, int order);
  * triangular solve (I + L_j) h = V_j^T w with L_j the strictly lower triangle of V_j^T V_j;
  * one vector reduction of the 2j - 1 inner products plus the norm per step; needs
  * m_max <= 64 (else EP_ERR_ARG at ep_workspace_size / ep_bind_workspace).  mode -1
- * (default): 1 when m_max <= 64, else 0.  Batches always use mode 0 (one workgroup per
- * instance).  Both forms give the same H and V up to rounding. */
+ * (default): 1 when m_max <= 64, else 0.  Batches always use mode 0.  Both forms give the same H and V up to rounding. */
 ep_status ep_set_orthogonalization(ep_ctx* ctx, int mode);
 /* The form in effect (after binding) or that binding would choose. */
 ep_status ep_get_orthogonalization(ep_ctx* ctx, int* mode);
@@ -325,7 +324,9 @@ ep_status ep_expv(ep_ctx* ctx, const double* u_lin_dev, double tau, double pscal
 /* ------------------------------------------------------------------ batches
  * A batch context advances many independent instances (own mesh, material, loads and
  * state) together: every instance's projections run inside one persistent launch per
- * step, one workgroup per instance, each with its own subspace size.  Instances are
+ * step (per material model), each instance with its own subspace size, on a workgroup of
+ * its own (at binding), in a list of instances one workgroup steps one after the other, or
+ * on a team of workgroups (see ep_batch_plan).  Instances are
  * added after ep_create and before ep_bind_workspace; the single-instance setup calls
  * are then not used.  The Krylov / precision settings apply to all instances.
  * Device-side failures are per instance: a failed instance stops advancing while the
