@@ -51,7 +51,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, ExpvArgs& a, const KrylovCfg
       a.out_mode = 0;
     }
     __syncthreads();
-    expv_body<T, MODEL, Team, 0, 2, 8, kLBBatch>(tm, a, lw, lv, red, yb, flag, X);
+    expv_body<T, MODEL, Team, 0, 2, 8, kLBBatch, 1>(tm, a, lw, lv, red, yb, flag, X);
   } else {
     const int nhist = B.nhist, hnew = B.hist_new, hold = B.hist_old;
     int reserve = -1;
@@ -86,7 +86,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, ExpvArgs& a, const KrylovCfg
       a.out_mode = 1;
     }
     __syncthreads();
-    expv_body<T, MODEL, Team, 0, 2, 8, kLBBatch>(tm, a, lw, lv, red, yb, flag, X);
+    expv_body<T, MODEL, Team, 0, 2, 8, kLBBatch, 1>(tm, a, lw, lv, red, yb, flag, X);
     if (tm.dead || read_err(&B.W.ctrl->err) != 0) return false;
     __syncthreads();                             // every lane is done reading a
     if (w0) {
@@ -103,7 +103,7 @@ __device__ bool device_step(Team& tm, BatchInst& B, ExpvArgs& a, const KrylovCfg
       a.out_mode = 0;
     }
     __syncthreads();
-    expv_body<T, MODEL, Team, 0, 2, 8, kLBBatch>(tm, a, lw, lv, red, yb, flag, X);
+    expv_body<T, MODEL, Team, 0, 2, 8, kLBBatch, 1>(tm, a, lw, lv, red, yb, flag, X);
     __syncthreads();                             // every lane is done reading B and a
     if (w0) {
       if (nhist == 0) {

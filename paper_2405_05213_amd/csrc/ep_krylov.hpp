@@ -94,7 +94,7 @@ __device__ __forceinline__ int read_err(const int* err) {
 // K_e x_e.  The FP32 kernels keep the quadrature form: K_e rounded to FP32 no longer maps
 // rigid motions to zero force, and its rounding costs about four orders of magnitude of
 // energy accuracy on a bending cantilever.
-template <typename T, int MODEL, int NPE = 8>
+template <typename T, int MODEL, int NPE = 8, int EL = 0>
 __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, const double* src,
                                                          double hinv, T* F, int rank, int G, const T* ke) {
   bool okA = true;
@@ -116,7 +116,10 @@ __device__ __forceinline__ bool phase_elements(const Mesh& M, const OpArgs& op, 
         return true;
       }
     }
-    if (elem_lanes<T, MODEL>() == 8) {
+    // EL: lanes per element chosen by the kernel (0: elem_lanes) - the batch kernel takes one
+    // lane per element in FP64 too (its workgroups are latency-bound on a mesh each)
+    constexpr int lanes = EL ? EL : elem_lanes<T, MODEL>();
+    if (lanes == 8) {
       // 8 lanes per element (one per Gauss point); the loop bound is uniform in each lane group
       for (int e = (rank * blockDim.x + threadIdx.x) >> 3; e < M.n_elems; e += (G * blockDim.x) >> 3)
         okA &= elem_force_qp<T, MODEL>(M, op, e, src, hinv, true, F);
@@ -234,7 +237,7 @@ __device__ __forceinline__ int check_point(Team& tm, const ExpvArgs& A, int j, d
 
 // X <- exp(f A) X on entry ||X|| = beta (SCH = 4: exp(f Omega) X).  Every workgroup returns
 // the same result.
-template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8, int LB = 1>
+template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8, int LB = 1, int EL = 0>
 __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
                               double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
@@ -279,7 +282,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     // ---- operator apply, part 1: element forces of the u-part of v_{j-1}
     bool okA;
     if constexpr (SCH == 4) okA = phase_elements_m4<T, MODEL>(M, A.op, src, hinv, F, F2, tm.rank, tm.G, (const T*)X.ke);
-    else okA = phase_elements<T, MODEL, NPE>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
+    else okA = phase_elements<T, MODEL, NPE, EL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;
     {
@@ -449,7 +452,7 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
 
 // Compact-WY form of the projection (see the file header).  Per step: the operator barrier,
 // one vector all-reduce of the 2j - 1 inner products, the fenced norm all-reduce.
-template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8, int LB = 1>
+template <typename T, int MODEL, class Team, int SCH = 2, int NPE = 8, int LB = 1, int EL = 0>
 __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double beta, int hint, double pscale,
                                   double* lw, double* lv, double* red, double* yb, int* flag, const KLds& X) {
   const Mesh& M = A.M;
@@ -483,7 +486,7 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
   for (int j = 1; j <= mcap; ++j) {
     bool okA;
     if constexpr (SCH == 4) okA = phase_elements_m4<T, MODEL>(M, A.op, src, hinv, F, F2, tm.rank, tm.G, (const T*)X.ke);
-    else okA = phase_elements<T, MODEL, NPE>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
+    else okA = phase_elements<T, MODEL, NPE, EL>(M, A.op, src, hinv, F, tm.rank, tm.G, (const T*)X.ke);
     if (!okA) atomicCAS(&W.ctrl->err, 0, kErrInverted);
     if (!tm.sync(flag)) return R;
     {
@@ -673,7 +676,7 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
 
 // wbar_out = exp(tau A) wbar_in with the sticky substep count and subspace-size hint of
 // this projection kind; writes statistics and sticky errors.
-template <typename T, int MODEL, class Team, int ORTHO = 0, int SCH = 2, int NPE = 8, int LB = 1>
+template <typename T, int MODEL, class Team, int ORTHO = 0, int SCH = 2, int NPE = 8, int LB = 1, int EL = 0>
 __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, double* red, double* yb,
                           int* flag, const KLds& cx) {
   const Mesh& M = A.M;
@@ -714,9 +717,9 @@ __device__ void expv_body(Team& tm, const ExpvArgs& A, double* lw, double* lv, d
     for (int sub = 0; sub < k; ++sub) {
       ProjResult r;
       if constexpr (Team::kVecReduce && ORTHO == 1)
-        r = project_cwy<T, MODEL, Team, SCH, NPE, LB>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+        r = project_cwy<T, MODEL, Team, SCH, NPE, LB, EL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       else
-        r = project<T, MODEL, Team, SCH, NPE, LB>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
+        r = project<T, MODEL, Team, SCH, NPE, LB, EL>(tm, A, A.op.tau / k, beta, hint_run, pscale, lw, lv, red, yb, flag, cx);
       if (tm.dead) return;
       nmv += r.nmv;
       if (r.status != 0) { status = r.status; ok = false; break; }
