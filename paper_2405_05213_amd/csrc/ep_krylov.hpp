@@ -25,17 +25,19 @@ namespace ep {
 
 constexpr double kBreakdown = 1e-14;
 
-// One workgroup acting alone (batched instances): team barrier = workgroup barrier.
+// One workgroup acting alone (batched instances): team barrier = workgroup barrier; sums
+// with one barrier each, alternating between the two halves of the reduction scratch.
 struct BlockTeam {
   static constexpr bool kVecReduce = false;
   int G = 1, rank = 0;
   bool dead = false;
+  unsigned sel = 0;
   __device__ bool sync(int*) {
     __syncthreads();
     return true;
   }
-  __device__ double allreduce(double p, double* red, int*, bool = false) { return block_sum(p, red); }
-  __device__ double post(double p, double* red, int*, bool) { return block_sum(p, red); }
+  __device__ double allreduce(double p, double* red, int*, bool = false) { return block_sum2(p, red, sel); }
+  __device__ double post(double p, double* red, int*, bool) { return block_sum2(p, red, sel); }
   __device__ double wait(double p, int*, bool, double* = nullptr) { return p; }
 };
 
