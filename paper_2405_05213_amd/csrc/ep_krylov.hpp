@@ -64,10 +64,11 @@ constexpr int kPF = 4;
 // LB of the projections).  The slices may sit in LDS or in device memory behind one generic
 // pointer, so a store can alias any later load and would otherwise hold back the next entry's
 // loads for a full memory round trip.  Worth it where a thread owns many entries (a batch
-// instance on one workgroup: 8.63 -> 7.31 ms per rubber-batch step); a cost where it owns about
-// one (the single-instance team: c2 6.43 -> 6.54 ms), so the batch kernel uses 4, the team
-// kernel 1.
-constexpr int kLBBatch = 4;
+// instance on one workgroup: 8.63 -> 7.31 ms per rubber-batch step with 4); a cost where it
+// owns about one (the single-instance team: c2 6.43 -> 6.54 ms), so the team kernel uses 1.
+// The batch kernel uses 2: with its registers already scarce, 2 / 4 / 8 give 4.07 / 4.16 /
+// 4.36 ms per planned rubber-batch step.
+constexpr int kLBBatch = 2;
 
 __device__ __forceinline__ void prefetch_row(double (&pf)[kPF], const double* row, int nloc) {
 #pragma unroll
