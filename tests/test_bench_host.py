@@ -47,7 +47,7 @@ def test_committed_record_describes_the_headline_launch():
     with open(bench.TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     probs = batch_instances(256, seed=5, dt=6.25e-6)
-    assert rec["workload"] == bench.batch_workload(probs, 6.25e-6, 32)
+    assert rec["workload"] == bench.batch_workload(probs, 6.25e-6, 32, bench.CHECK_EVERY)
     assert rec["precision"] == "mixed_f32"
     assert rec["traffic_bytes_per_launch"] > 0 and len(rec["kernel_sources_sha256"]) == 64
 

@@ -130,12 +130,13 @@ def test_arnoldi_matches_oracle(name, over, workgroups, ortho):
         assert maxrel(from_gpu_vec(orc, Vg[j]), Vo[j]) < 1e-8
 
 
+@pytest.mark.parametrize("check_every", [4, 1])
 @pytest.mark.parametrize("ortho", [0, 1])
 @pytest.mark.parametrize("dt,workgroups", [(2e-5, 1), (1e-4, 2), (4e-4, 3)])
-def test_expv_matches_oracle(dt, workgroups, ortho):
-    say(f"[expv] c1 dt={dt} G={workgroups} ortho={ortho}")
+def test_expv_matches_oracle(dt, workgroups, ortho, check_every):
+    say(f"[expv] c1 dt={dt} G={workgroups} ortho={ortho} check_every={check_every}")
     p = config("c1")
-    ctx, orc = pair(p, m_max=48, workgroups=workgroups, ortho=ortho)
+    ctx, orc = pair(p, m_max=48, check_every=check_every, workgroups=workgroups, ortho=ortho)
     rng = np.random.default_rng(11)
     N = orc.N
     w = np.concatenate([orc.Mh * rng.normal(0, 1e-5, N), orc.Mh * rng.normal(0, 1e-2, N), [1.0]])
@@ -143,18 +144,21 @@ def test_expv_matches_oracle(dt, workgroups, ortho):
     y = torch.zeros(Lp, dtype=torch.float64, device=DEV)
     m, k, eps = ctx.expv(None, dt, 1.0, _t(to_gpu_vec(orc, w, Lp)), y)
     yo, info = krylov.expv(lambda v, f: orc.A_apply(v, f, None, orc.P0bar), w, dt, tol=p.tol, m_max=48,
-                           check_every=4, state={})
+                           check_every=check_every, state={})
     assert k == info["k"] and m == info["m"][-1]
     assert maxrel(from_gpu_vec(orc, _np(y)), yo) < 1e-9
 
 
 @pytest.mark.parametrize("ortho", [0, 1])
-@pytest.mark.parametrize("mode", ["fixed", "adaptive"])
+@pytest.mark.parametrize("mode", ["fixed", "adaptive", "adaptive_every_step"])
 def test_linear_steps_c1(mode, ortho):
-    """200 steps of the 10x2x2 linear cantilever (dt 1e-4, tol 1e-10) against the oracle."""
+    """200 steps of the 10x2x2 linear cantilever (dt 1e-4, tol 1e-10) against the oracle; the
+    adaptive runs estimate the error every fourth or every Arnoldi step and must pick the
+    oracle's subspace size at every step."""
     say(f"[steps] c1 linear {mode} ortho={ortho}")
     p = config("c1")
-    kw = dict(m_max=64) if mode == "adaptive" else dict(m_max=64, m_fixed=32, k_fixed=1)
+    kw = {"fixed": dict(m_max=64, m_fixed=32, k_fixed=1), "adaptive": dict(m_max=64),
+          "adaptive_every_step": dict(m_max=64, check_every=1)}[mode]
     kw["ortho"] = ortho
     ctx, orc = pair(p, **kw)
     ctx.step(p.dt, p.n_steps)
@@ -167,7 +171,7 @@ def test_linear_steps_c1(mode, ortho):
     ko, so_, wo = orc.energies()
     assert abs(ke - ko) <= 1e-8 * (ko + so_) and abs(se - so_) <= 1e-8 * (ko + so_)
     assert abs(we - wo) <= 1e-8 * abs(wo)
-    if mode == "adaptive":
+    if mode != "fixed":
         log = ctx.step_log(p.n_steps)
         mo = np.array([r["corr"]["m"][0] for r in orc.log])
         assert np.array_equal(log["m_corr"], mo)
@@ -233,25 +237,36 @@ def test_congruence_detection(name, over, mode, expect):
     assert g >= 1 and chunk >= 64 and g * chunk >= 2 * 3 * p.n_nodes + 1
 
 
-@pytest.mark.parametrize("prec,tol", [("f64", 1e-7), ("mixed_f32", 3e-5)])
-def test_energy_conservation_free_vibration(prec, tol):
-    """Unloaded cantilever with random initial velocity, 60 adaptive steps: the propagator
-    conserves the discrete energy up to the Krylov tolerance (FP64: ~1e-8 measured) and the
-    FP32 operator's rounding: 5e-6 - 1.6e-5 measured, depending on the adaptive path (small
-    exponential implementations that agree to 1e-13 change the subspace size at some steps);
-    an element kernel that loses the deformation to a large common translation drifts 1e-3.
-    The FP32 figure is not held to the 1e-6 energy gate of the batched rubber blocks: on this
-    stiff steel beam the FP32 operator itself is only accurate to 2-3e-6 (a bending field is a
-    small difference of large element forces), so the energy cannot be conserved below that."""
-    say(f"[energy] c2 20x4x4 {prec}")
+# FP32 operator error on this steel beam (operator parity: 2-3e-6 relative); each step's
+# rounding perturbs the energy by about that much, independently of the others
+FP32_OP_ERR = 3e-6
+
+
+@pytest.mark.parametrize("prec,fixed", [("f64", False), ("f64", True), ("mixed_f32", False), ("mixed_f32", True)])
+def test_energy_conservation_free_vibration(prec, fixed):
+    """Unloaded cantilever with random initial velocity, 60 steps (adaptive subspace, or fixed
+    at m = 48 with 2 substeps): the propagator conserves the discrete energy up to the Krylov
+    tolerance in FP64 (~1e-8 adaptive, ~3e-9 at the fixed m) and up to the FP32 operator's
+    rounding in the mixed form, where each step adds an independent error of about the
+    operator's relative error e (2-3e-6 on this beam: a bending field is a small difference of
+    large element forces), so the drift is a random walk bounded by about sqrt(n) e: the test
+    takes 1.3 sqrt(n) e (3e-5 at n = 60; measured 5e-6 - 1.6e-5, the same at the fixed and the
+    adaptive subspace, and of either sign over 20 ... 120 steps).  This is outside the 1e-6
+    energy gate of the batched rubber blocks, which their FP32 form meets.  An element kernel
+    that loses the deformation to a large common translation drifts 1e-3."""
+    say(f"[energy] c2 20x4x4 {prec} {'fixed m' if fixed else 'adaptive'}")
     p = config("c2", nx=20, ny=4, nz=4)
-    ctx, _ = pair(p, precision=prec, m_max=64)
+    kw = dict(m_max=64, m_fixed=48, k_fixed=2) if fixed else dict(m_max=64)
+    ctx, _ = pair(p, precision=prec, **kw)
+    n = 60
+    tol = 1e-7 if prec == "f64" else 1.3 * np.sqrt(n) * FP32_OP_ERR
     e0 = ctx.energy()
-    ctx.step(p.dt, 60)
+    ctx.step(p.dt, n)
     e1 = ctx.energy()
     E0, E1 = e0[0] + e0[1] - e0[2], e1[0] + e1[1] - e1[2]
-    say(f"  relative energy drift {abs(E1 - E0) / (e0[0] + e0[1]):.2e}")
+    say(f"  relative energy drift {abs(E1 - E0) / (e0[0] + e0[1]):.2e} (bound {tol:.1e})")
     assert abs(E1 - E0) <= tol * (e0[0] + e0[1])
+    ctx.close()
 
 
 @pytest.mark.parametrize("ortho", [0, 1])
