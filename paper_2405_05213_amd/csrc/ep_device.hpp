@@ -428,8 +428,136 @@ __device__ __forceinline__ void rest_lame(int model, const double* mp, double& l
 }
 
 // ---------------------------------------------------------------------------------------
+// Modal form of a trilinear field on the hex8 reference element.  With the signs (sx, sy, sz)
+// of node a, N_a = (1 + sx xi)(1 + sy eta)(1 + sz zeta) / 8, so a field sum_a x_a N_a is
+//   m0 + m1 xi + m2 eta + m3 zeta + m4 xi eta + m5 eta zeta + m6 xi zeta + m7 xi eta zeta,
+// m_c = (1/8) sum_a h_c(a) x_a, h_c(a) the product of node a's signs in the directions of
+// mode c.  Modes 1..7 carry the gradient: a reference derivative at a point costs 3 FMAs
+// instead of an 8-node sum, and the force scatter becomes an update of 7 modal sums per
+// component at each point plus one transform back to the nodes per element.
+// Stored mode order: xi, eta, zeta, xi eta, eta zeta, xi zeta, xi eta zeta.
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void to_modes(const T (&x)[8][3], T (&m)[3][7]) {
+  constexpr int nd[2][2][2] = {{{0, 4}, {3, 7}}, {{1, 5}, {2, 6}}};   // VTK node at [bx][by][bz]
+  const T h = T(0.125);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T s[2][2], d[2][2];   // sum and difference over xi, [by][bz]
+#pragma unroll
+    for (int by = 0; by < 2; ++by)
+#pragma unroll
+      for (int bz = 0; bz < 2; ++bz) {
+        s[by][bz] = x[nd[1][by][bz]][i] + x[nd[0][by][bz]][i];
+        d[by][bz] = x[nd[1][by][bz]][i] - x[nd[0][by][bz]][i];
+      }
+    T ss[2], sd[2], ds[2], dd[2];   // then over eta, [bz]
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz) {
+      ss[bz] = s[1][bz] + s[0][bz];
+      sd[bz] = s[1][bz] - s[0][bz];
+      ds[bz] = d[1][bz] + d[0][bz];
+      dd[bz] = d[1][bz] - d[0][bz];
+    }
+    m[i][0] = h * (ds[1] + ds[0]);
+    m[i][1] = h * (sd[1] + sd[0]);
+    m[i][2] = h * (ss[1] - ss[0]);
+    m[i][3] = h * (dd[1] + dd[0]);
+    m[i][4] = h * (sd[1] - sd[0]);
+    m[i][5] = h * (ds[1] - ds[0]);
+    m[i][6] = h * (dd[1] - dd[0]);
+  }
+}
+
+// Reference point of Gauss point q (signs of node q times 1/sqrt(3)) and its pair products.
+template <typename T>
+struct GaussPt {
+  T xi, eta, zeta, ez, xz, xe;
+  __device__ __forceinline__ explicit GaussPt(int q) {
+    xi = T(kGauss) * T(node_sx(q));
+    eta = T(kGauss) * T(node_sy(q));
+    zeta = T(kGauss) * T(node_sz(q));
+    ez = eta * zeta;
+    xz = xi * zeta;
+    xe = xi * eta;
+  }
+};
+
+// G[i][k] = d x_i / d X_k at the point: reference derivatives from the modes, then Jinv
+template <typename T>
+__device__ __forceinline__ void modal_grad(const T (&m)[3][7], const GaussPt<T>& P, const T* Jinv, T (&G)[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T d0 = m[i][0], d1 = m[i][1], d2 = m[i][2];
+    d0 += m[i][3] * P.eta;
+    d0 += m[i][5] * P.zeta;
+    d0 += m[i][6] * P.ez;
+    d1 += m[i][3] * P.xi;
+    d1 += m[i][4] * P.zeta;
+    d1 += m[i][6] * P.xz;
+    d2 += m[i][5] * P.xi;
+    d2 += m[i][4] * P.eta;
+    d2 += m[i][6] * P.xe;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) G[i][k] = d0 * Jinv[0 * 3 + k] + d1 * Jinv[1 * 3 + k] + d2 * Jinv[2 * 3 + k];
+  }
+}
+
+// Modal force sums g += the point's contribution: st = wdet S Jinv^T weighs the three
+// reference derivatives, each mode takes its own derivative at the point
+template <typename T>
+__device__ __forceinline__ void modal_scatter(const T (&S)[3][3], const T* Jinv, T wdet, const GaussPt<T>& P,
+                                              T (&g)[3][7]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    T st[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      st[j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
+    g[i][0] += st[0];
+    g[i][1] += st[1];
+    g[i][2] += st[2];
+    g[i][3] += st[0] * P.eta;
+    g[i][3] += st[1] * P.xi;
+    g[i][4] += st[1] * P.zeta;
+    g[i][4] += st[2] * P.eta;
+    g[i][5] += st[0] * P.zeta;
+    g[i][5] += st[2] * P.xi;
+    g[i][6] += st[0] * P.ez;
+    g[i][6] += st[1] * P.xz;
+    g[i][6] += st[2] * P.xe;
+  }
+}
+
+// Nodal forces from the modal sums: f[a][i] = (1/8) sum_c h_c(a) g_c,i, i.e. per node
+//   (1/8) [sx (c + sy d) + sy a + b],  a = g_eta + sz g_eta.zeta, b = sz g_zeta,
+//   c = g_xi + sz g_xi.zeta, d = g_xi.eta + sz g_xi.eta.zeta
+template <typename T>
+__device__ __forceinline__ void from_modes(const T (&g)[3][7], T (&f)[8][3]) {
+  constexpr int nd[2][2][2] = {{{0, 4}, {3, 7}}, {{1, 5}, {2, 6}}};
+  const T h = T(0.125);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz) {
+      const T a = bz ? g[i][1] + g[i][4] : g[i][1] - g[i][4];
+      const T b = bz ? g[i][2] : -g[i][2];
+      const T c = bz ? g[i][0] + g[i][5] : g[i][0] - g[i][5];
+      const T d = bz ? g[i][3] + g[i][6] : g[i][3] - g[i][6];
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        const T p = by ? b + a : b - a;
+        const T r = by ? c + d : c - d;
+        f[nd[1][by][bz]][i] = h * (p + r);
+        f[nd[0][by][bz]][i] = h * (p - r);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Element force of one element: f_e = sum_q w detJ S(grad x) . grad N, S the (secant)
-// stress of the material at the operator's linearisation points.
+// stress of the material at the operator's linearisation points (one lane per element;
+// the fields enter in modal form).
 //   x_a = src[dof] * srcscale (* mih[dof] when scale_mih)
 // ---------------------------------------------------------------------------------------
 template <typename T, int MODEL>
@@ -442,43 +570,48 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
   // the forces depend on gradients only, and a large common translation would otherwise
   // cost the deformation its significant bits.
   constexpr bool shift = sizeof(T) == 4;
-  T x[8][3];
-  double x0[3] = {0.0, 0.0, 0.0};
+  T xm[3][7];
+  {
+    T x[8][3];
+    double x0[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < 8; ++a)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const size_t d = (size_t)nd[a] * 3 + i;
-      double v = src[d] * srcscale;
-      if (scale_mih) v *= M.mih[d];
-      if (shift && a == 0) x0[i] = v;
-      x[a][i] = T(v - x0[i]);
-      f[a][i] = T(0);
-    }
+      for (int i = 0; i < 3; ++i) {
+        const size_t d = (size_t)nd[a] * 3 + i;
+        double v = src[d] * srcscale;
+        if (scale_mih) v *= M.mih[d];
+        if (shift && a == 0) x0[i] = v;
+        x[a][i] = T(v - x0[i]);
+      }
+    to_modes(x, xm);
+  }
   const int nsets = (MODEL == kLinear) ? 0 : op.nsets;
-  T u0[8][3], u1[8][3];
-  if (nsets >= 1) {
-    const double* ul = op.ulin[0];
+  T um0[3][7], um1[3][7];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+  for (int k = 0; k < 2; ++k) {
+    if (nsets > k) {
+      const double* ul = op.ulin[k];
+      T u[8][3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        u0[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          u[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
+      to_modes(u, k == 0 ? um0 : um1);
+    }
   }
-  if (nsets >= 2) {
-    const double* ul = op.ulin[1];
+  T g[3][7];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        u1[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
-  }
+    for (int c = 0; c < 7; ++c) g[i][c] = T(0);
   double lam_d, mu_d;
   rest_lame(M.model, M.mp, lam_d, mu_d);
   const T lam = T(lam_d), mu = T(mu_d);
   bool ok = true;
   for (int q = 0; q < 8; ++q) {
-    const QFactors<T> Q(q);
+    const GaussPt<T> P(q);
     T Jinv[9], wdet;
     const size_t gi = (M.congruent ? (size_t)q : (size_t)e * 8 + q) * 10;
     if (sizeof(T) == 8) {
@@ -491,7 +624,7 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
       wdet = T(M.geo32[gi + 9]);
     }
     T X[3][3];
-    grad_at(Q, x, Jinv, X);
+    modal_grad(xm, P, Jinv, X);
     T S[3][3];
     if (nsets == 0) {
       const T tr = X[0][0] + X[1][1] + X[2][2];
@@ -507,26 +640,27 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
       if constexpr (MODEL == kSVK) {
         T Du[3][3];
         SecantSVK<T> sv;
-        grad_at(Q, u0, Jinv, Du);
+        modal_grad(um0, P, Jinv, Du);
         svk_coeffs(Du, lam, mu, sv);
         svk_apply(sv, lam, mu, T(op.wts[0]), X, S);
         if (nsets >= 2) {
-          grad_at(Q, u1, Jinv, Du);
+          modal_grad(um1, P, Jinv, Du);
           svk_coeffs(Du, lam, mu, sv);
           svk_apply(sv, lam, mu, T(op.wts[1]), X, S);
         }
       } else if (MODEL != kLinear) {
         T Du[3][3];
-        grad_at(Q, u0, Jinv, Du);
+        modal_grad(um0, P, Jinv, Du);
         ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[0]), S);
         if (nsets >= 2) {
-          grad_at(Q, u1, Jinv, Du);
+          modal_grad(um1, P, Jinv, Du);
           ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[1]), S);
         }
       }
     }
-    scatter_at(Q, S, Jinv, wdet, f);
+    modal_scatter(S, Jinv, wdet, P, g);
   }
+  from_modes(g, f);
   return ok;
 }
 
