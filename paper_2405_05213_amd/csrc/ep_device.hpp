@@ -428,6 +428,111 @@ __device__ __forceinline__ void rest_lame(int model, const double* mp, double& l
 }
 
 // ---------------------------------------------------------------------------------------
+// Element force of one element in nodal form (8-node sums at each Gauss point):
+// f_e = sum_q w detJ S(grad x) . grad N.  The linear material keeps this form: in the
+// kernels of the linear operator the modal form's extra live values cost register spills
+// (the single-instance FP64 kernel: 97 -> 269 spilled registers) for little VALU work saved.
+//   x_a = src[dof] * srcscale (* mih[dof] when scale_mih)
+// ---------------------------------------------------------------------------------------
+template <typename T, int MODEL>
+__device__ __forceinline__ bool elem_force_nodal(const Mesh& M, const OpArgs& op, int e, const double* src,
+                                           double srcscale, bool scale_mih, T (&f)[8][3]) {
+  int nd[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
+  // In FP32 the element's inputs are taken relative to node 0 (in FP64 before rounding):
+  // the forces depend on gradients only, and a large common translation would otherwise
+  // cost the deformation its significant bits.
+  constexpr bool shift = sizeof(T) == 4;
+  T x[8][3];
+  double x0[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const size_t d = (size_t)nd[a] * 3 + i;
+      double v = src[d] * srcscale;
+      if (scale_mih) v *= M.mih[d];
+      if (shift && a == 0) x0[i] = v;
+      x[a][i] = T(v - x0[i]);
+      f[a][i] = T(0);
+    }
+  const int nsets = (MODEL == kLinear) ? 0 : op.nsets;
+  T u0[8][3], u1[8][3];
+  if (nsets >= 1) {
+    const double* ul = op.ulin[0];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        u0[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
+  }
+  if (nsets >= 2) {
+    const double* ul = op.ulin[1];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        u1[a][i] = T(ul[(size_t)nd[a] * 3 + i] - (shift ? ul[(size_t)nd[0] * 3 + i] : 0.0));
+  }
+  double lam_d, mu_d;
+  rest_lame(M.model, M.mp, lam_d, mu_d);
+  const T lam = T(lam_d), mu = T(mu_d);
+  bool ok = true;
+  for (int q = 0; q < 8; ++q) {
+    const QFactors<T> Q(q);
+    T Jinv[9], wdet;
+    const size_t gi = (M.congruent ? (size_t)q : (size_t)e * 8 + q) * 10;
+    if (sizeof(T) == 8) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo[gi + k]);
+      wdet = T(M.geo[gi + 9]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) Jinv[k] = T(M.geo32[gi + k]);
+      wdet = T(M.geo32[gi + 9]);
+    }
+    T X[3][3];
+    grad_at(Q, x, Jinv, X);
+    T S[3][3];
+    if (nsets == 0) {
+      const T tr = X[0][0] + X[1][1] + X[2][2];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S[i][k] = mu * (X[i][k] + X[k][i]) + (i == k ? lam * tr : T(0));
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) S[i][k] = T(0);
+      if constexpr (MODEL == kSVK) {
+        T Du[3][3];
+        SecantSVK<T> sv;
+        grad_at(Q, u0, Jinv, Du);
+        svk_coeffs(Du, lam, mu, sv);
+        svk_apply(sv, lam, mu, T(op.wts[0]), X, S);
+        if (nsets >= 2) {
+          grad_at(Q, u1, Jinv, Du);
+          svk_coeffs(Du, lam, mu, sv);
+          svk_apply(sv, lam, mu, T(op.wts[1]), X, S);
+        }
+      } else if (MODEL != kLinear) {
+        T Du[3][3];
+        grad_at(Q, u0, Jinv, Du);
+        ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[0]), S);
+        if (nsets >= 2) {
+          grad_at(Q, u1, Jinv, Du);
+          ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[1]), S);
+        }
+      }
+    }
+    scatter_at(Q, S, Jinv, wdet, f);
+  }
+  return ok;
+}
+
+// ---------------------------------------------------------------------------------------
 // Modal form of a trilinear field on the hex8 reference element.  With the signs (sx, sy, sz)
 // of node a, N_a = (1 + sx xi)(1 + sy eta)(1 + sz zeta) / 8, so a field sum_a x_a N_a is
 //   m0 + m1 xi + m2 eta + m3 zeta + m4 xi eta + m5 eta zeta + m6 xi zeta + m7 xi eta zeta,
@@ -557,12 +662,13 @@ __device__ __forceinline__ void from_modes(const T (&g)[3][7], T (&f)[8][3]) {
 // ---------------------------------------------------------------------------------------
 // Element force of one element: f_e = sum_q w detJ S(grad x) . grad N, S the (secant)
 // stress of the material at the operator's linearisation points (one lane per element;
-// the fields enter in modal form).
+// the secant materials take the fields in modal form, the linear one the nodal form).
 //   x_a = src[dof] * srcscale (* mih[dof] when scale_mih)
 // ---------------------------------------------------------------------------------------
 template <typename T, int MODEL>
 __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int e, const double* src,
                                            double srcscale, bool scale_mih, T (&f)[8][3]) {
+  if constexpr (MODEL == kLinear) return elem_force_nodal<T, MODEL>(M, op, e, src, srcscale, scale_mih, f);
   int nd[8];
 #pragma unroll
   for (int a = 0; a < 8; ++a) nd[a] = M.conn[(size_t)e * 8 + a];
