@@ -115,12 +115,18 @@ __device__ __forceinline__ float ep_log1p(float x) { return log1pf(x); }
 __device__ __forceinline__ double ep_exp(double x) { return exp(x); }
 __device__ __forceinline__ float ep_exp(float x) { return expf(x); }
 
+// 1/x: correctly rounded in FP64; in FP32 the hardware reciprocal (1 ulp), whose error is
+// far below the FP32 operator's own rounding (the IEEE division costs about ten instructions
+// in the secant stress's Gauss-point loop, which is bound by its instruction count)
+__device__ __forceinline__ double ep_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float ep_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // ln(1+x)/x, continuous through x = 0
 template <typename T>
 __device__ __forceinline__ T log_ratio(T x) {
   const T ax = x < T(0) ? -x : x;
-  if (ax < T(sizeof(T) == 8 ? 1e-8 : 1e-4)) return T(1) - T(0.5) * x + x * x / T(3);
-  return ep_log1p(x) / x;
+  if (ax < T(sizeof(T) == 8 ? 1e-8 : 1e-4)) return T(1) - T(0.5) * x + x * x * T(1.0 / 3.0);
+  return ep_log1p(x) * ep_rcp(x);
 }
 
 // J^{-2/3} for J = 1 + x > 0: an FP32 estimate of y = J^{-1/3} refined by Newton steps on
@@ -278,7 +284,7 @@ __device__ __forceinline__ bool secant_stress_add(const T (&D)[3][3], const T (&
   const T J = T(1) + x;
   if (!(J > T(0))) return false;
   const T trX = X[0][0] + X[1][1] + X[2][2];
-  const T Jinv = T(1) / J;
+  const T Jinv = ep_rcp(J);
   T Fi[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
