@@ -471,6 +471,20 @@ static ep_status setup_inst(ep_ctx* c, Inst& I, int G, int chunk, int Gslots) {
   M.geo = dptr<double>(c, I.o_geo);
   M.geo32 = dptr<float>(c, I.o_geo32);
   M.congruent = hflags[1] ? 0 : 1;
+  // an axis-aligned box element has a diagonal Jacobian; the 8-node sums leave rounding
+  // residue of the order of 1e-17 relative off the diagonal, which the diagonal form drops
+  M.jdiag = 0;
+  if (M.congruent && I.npe == 8 && I.n_elems > 0) {
+    double g[8 * 10];
+    EP_HIP(c, hipMemcpy(g, M.geo, sizeof(g), hipMemcpyDeviceToHost));
+    bool diag = true;
+    for (int q = 0; q < 8; ++q) {
+      const double dmax = std::max(std::fabs(g[q * 10]), std::max(std::fabs(g[q * 10 + 4]), std::fabs(g[q * 10 + 8])));
+      for (int k = 0; k < 9; ++k)
+        if (k % 4 != 0 && !(std::fabs(g[q * 10 + k]) <= 1e-12 * dmax)) diag = false;
+    }
+    M.jdiag = diag ? 1 : 0;
+  }
   M.mih = dptr<double>(c, I.o_mih);
   M.mh = dptr<double>(c, I.o_mh);
   M.p0bar = dptr<double>(c, I.o_p0bar);

@@ -45,6 +45,8 @@ struct Mesh {
   const double* geo;          // per quadrature point: Jinv (3x3 row major) + w*detJ
   const float* geo32;
   int congruent;              // 1: one geometry set shared by all elements
+  int jdiag;                  // 1: congruent hex8 mesh whose Gauss-point J^{-1} are diagonal
+                              // (axis-aligned boxes; off-diagonals are rounding residue)
   const double* ke;           // congruent meshes: rest-state element stiffness (24 x kKeLd),
                               // null otherwise
   int lat[3];                 // congruent lattice (node i + (nx+1)(j + (ny+1)k), VTK order):

@@ -595,8 +595,11 @@ struct GaussPt {
 };
 
 // G[i][k] = d x_i / d X_k at the point: reference derivatives from the modes, then Jinv
+// (only its diagonal when jd: axis-aligned boxes)
 template <typename T>
-__device__ __forceinline__ void modal_grad(const T (&m)[3][7], const GaussPt<T>& P, const T* Jinv, T (&G)[3][3]) {
+__device__ __forceinline__ void modal_grad(const T (&m)[3][7], const GaussPt<T>& P, const T* Jinv, bool jd,
+                                           T (&G)[3][3]) {
+  T d[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     T d0 = m[i][0], d1 = m[i][1], d2 = m[i][2];
@@ -609,22 +612,50 @@ __device__ __forceinline__ void modal_grad(const T (&m)[3][7], const GaussPt<T>&
     d2 += m[i][5] * P.xi;
     d2 += m[i][4] * P.eta;
     d2 += m[i][6] * P.xe;
+    d[i][0] = d0;
+    d[i][1] = d1;
+    d[i][2] = d2;
+  }
+  if (jd) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) G[i][k] = d0 * Jinv[0 * 3 + k] + d1 * Jinv[1 * 3 + k] + d2 * Jinv[2 * 3 + k];
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) G[i][k] = d[i][k] * Jinv[4 * k];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        G[i][k] = d[i][0] * Jinv[0 * 3 + k] + d[i][1] * Jinv[1 * 3 + k] + d[i][2] * Jinv[2 * 3 + k];
   }
 }
 
 // Modal force sums g += the point's contribution: st = wdet S Jinv^T weighs the three
 // reference derivatives, each mode takes its own derivative at the point
 template <typename T>
-__device__ __forceinline__ void modal_scatter(const T (&S)[3][3], const T* Jinv, T wdet, const GaussPt<T>& P,
+__device__ __forceinline__ void modal_scatter(const T (&S)[3][3], const T* Jinv, bool jd, T wdet, const GaussPt<T>& P,
                                               T (&g)[3][7]) {
+  T sw[3][3];
+  if (jd) {
+    const T w0 = wdet * Jinv[0], w1 = wdet * Jinv[4], w2 = wdet * Jinv[8];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sw[i][0] = S[i][0] * w0;
+      sw[i][1] = S[i][1] * w1;
+      sw[i][2] = S[i][2] * w2;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        sw[i][j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
+  }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     T st[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      st[j] = wdet * (S[i][0] * Jinv[j * 3 + 0] + S[i][1] * Jinv[j * 3 + 1] + S[i][2] * Jinv[j * 3 + 2]);
+    for (int j = 0; j < 3; ++j) st[j] = sw[i][j];
     g[i][0] += st[0];
     g[i][1] += st[1];
     g[i][2] += st[2];
@@ -721,6 +752,7 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
   double lam_d, mu_d;
   rest_lame(M.model, M.mp, lam_d, mu_d);
   const T lam = T(lam_d), mu = T(mu_d);
+  const bool jd = M.jdiag != 0;
   bool ok = true;
   for (int q = 0; q < 8; ++q) {
     const GaussPt<T> P(q);
@@ -736,7 +768,7 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
       wdet = T(M.geo32[gi + 9]);
     }
     T X[3][3];
-    modal_grad(xm, P, Jinv, X);
+    modal_grad(xm, P, Jinv, jd, X);
     T S[3][3];
     if (nsets == 0) {
       const T tr = X[0][0] + X[1][1] + X[2][2];
@@ -752,25 +784,25 @@ __device__ __forceinline__ bool elem_force(const Mesh& M, const OpArgs& op, int 
       if constexpr (MODEL == kSVK) {
         T Du[3][3];
         SecantSVK<T> sv;
-        modal_grad(um0, P, Jinv, Du);
+        modal_grad(um0, P, Jinv, jd, Du);
         svk_coeffs(Du, lam, mu, sv);
         svk_apply(sv, lam, mu, T(op.wts[0]), X, S);
         if (nsets >= 2) {
-          modal_grad(um1, P, Jinv, Du);
+          modal_grad(um1, P, Jinv, jd, Du);
           svk_coeffs(Du, lam, mu, sv);
           svk_apply(sv, lam, mu, T(op.wts[1]), X, S);
         }
       } else if (MODEL != kLinear) {
         T Du[3][3];
-        modal_grad(um0, P, Jinv, Du);
+        modal_grad(um0, P, Jinv, jd, Du);
         ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[0]), S);
         if (nsets >= 2) {
-          modal_grad(um1, P, Jinv, Du);
+          modal_grad(um1, P, Jinv, jd, Du);
           ok &= secant_stress_add<T, MODEL>(Du, X, M.mp, T(op.wts[1]), S);
         }
       }
     }
-    modal_scatter(S, Jinv, wdet, P, g);
+    modal_scatter(S, Jinv, jd, wdet, P, g);
   }
   from_modes(g, f);
   return ok;
