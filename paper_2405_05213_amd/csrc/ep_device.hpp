@@ -1256,6 +1256,58 @@ __device__ __forceinline__ double gather_slots(const SlotMap& S, const T* F, int
   return s;
 }
 
+// The three summed forces of node A's DOFs in one pass: the node's position in the lattice
+// (or its slot list) once, and each slot's three components together; every component is
+// summed over the corners in the order of gather_slots, so the sums are the same numbers.
+template <typename T>
+__device__ __forceinline__ void gather_node(const SlotMap& S, const T* F, int A, double (&s)[3]) {
+  s[0] = s[1] = s[2] = 0.0;
+  if (S.lat) {
+    const int k = (int)(((double)A + 0.5) * S.rNXY);
+    const int r = A - k * S.NXY;
+    const int j = (int)(((double)r + 0.5) * S.rNX);
+    const int i = r - j * S.NX;
+    const int e0 = i + S.nx * (j + S.ny * k);
+    const bool x0 = i < S.nx, x1 = i > 0, y0 = j < S.ny, y1 = j > 0, z0 = k < S.nz, z1 = k > 0;
+    T f[8][3];
+    bool in[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const bool di = ((a + 1) >> 1) & 1, dj = (a >> 1) & 1, dk = a >> 2;
+      in[a] = (di ? x1 : x0) && (dj ? y1 : y0) && (dk ? z1 : z0);
+      const T* q = F + (e0 + S.base[a]) * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f[a][c] = in[a] ? q[c] : T(0);
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      if (in[a]) {
+        s[0] += double(f[a][0]);
+        s[1] += double(f[a][1]);
+        s[2] += double(f[a][2]);
+      }
+    return;
+  }
+  const int p0 = S.inc_ptr[A], p1 = S.inc_ptr[A + 1];
+  for (int p = p0; p < p1; p += 8) {
+    int sl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sl[u] = p + u < p1 ? S.inc[p + u] : -1;
+    T f[8][3];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) f[u][c] = sl[u] >= 0 ? F[(size_t)sl[u] * 3 + c] : T(0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (sl[u] >= 0) {
+        s[0] += double(f[u][0]);
+        s[1] += double(f[u][1]);
+        s[2] += double(f[u][2]);
+      }
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ double gather_force(const Mesh& M, const T* F, int A, int c) {
   return gather_slots(slot_map(M), F, A, c);

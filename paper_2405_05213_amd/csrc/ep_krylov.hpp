@@ -297,34 +297,83 @@ __device__ ProjResult project(Team& tm, const ExpvArgs& A, double f, double beta
     const double xs = src[2 * n3] * hinv * M.s_inv;      // s-entry of v_{j-1} / s0
     const SlotMap sm = slot_map(M);                       // not held across the element pass
     double part = 0.0;
-    for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
-      double w[LB], v0[LB];
+    if constexpr (SCH == 4) {
+      for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
+        double w[LB], v0[LB];
 #pragma unroll
-      for (int u = 0; u < LB; ++u) {
-        const int i = i0 + u * blockDim.x;
-        w[u] = 0.0;
-        v0[u] = 0.0;
-        if (i < nloc) {
-          const int g = c0 + i;
-          if constexpr (SCH == 4) {
-            w[u] = m4_entry<T, MODEL>(M, sm, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
-          } else if (g < n3) {
-            w[u] = f * (src[n3 + g] * hinv);
-          } else if (g < 2 * n3) {
-            const int d = g - n3;
-            const double s = gather_slots(sm, F, d / 3, d - (d / 3) * 3);
-            w[u] = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
+        for (int u = 0; u < LB; ++u) {
+          const int i = i0 + u * blockDim.x;
+          w[u] = 0.0;
+          v0[u] = 0.0;
+          if (i < nloc) {
+            w[u] = m4_entry<T, MODEL>(M, sm, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, c0 + i);
+            v0[u] = W.V[c0 + i];
           }
-          v0[u] = W.V[c0 + i];
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int i = i0 + u * blockDim.x;
+          if (i < nloc) {
+            lw[i] = w[u];
+            if (!lvV) lv[i] = v0[u];
+            part += w[u] * v0[u];
+          }
         }
       }
+    } else {
+      // own entries [0, uhi): u-part, w = f v-part of v_{j-1}; [uhi, vhi): v-part, from the
+      // element forces, node by node; [vhi, nloc): the s-row and padding, w = 0
+      const int uhi = min(nloc, max(0, n3 - c0));
+      const int vhi = min(nloc, max(uhi, 2 * n3 - c0));
+      for (int r = 0; r < 2; ++r) {
+        const int lo = r == 0 ? 0 : vhi, hi = r == 0 ? uhi : nloc;
+        for (int i0 = lo + threadIdx.x; i0 < hi; i0 += LB * blockDim.x) {
+          double w[LB], v0[LB];
 #pragma unroll
-      for (int u = 0; u < LB; ++u) {
-        const int i = i0 + u * blockDim.x;
-        if (i < nloc) {
-          lw[i] = w[u];
-          if (!lvV) lv[i] = v0[u];
-          part += w[u] * v0[u];
+          for (int u = 0; u < LB; ++u) {
+            const int i = i0 + u * blockDim.x;
+            w[u] = 0.0;
+            v0[u] = 0.0;
+            if (i < hi) {
+              if (r == 0) w[u] = f * (src[n3 + c0 + i] * hinv);
+              v0[u] = W.V[c0 + i];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < LB; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < hi) {
+              lw[i] = w[u];
+              if (!lvV) lv[i] = v0[u];
+              part += w[u] * v0[u];
+            }
+          }
+        }
+      }
+      if (uhi < vhi) {
+        const int a0 = (c0 + uhi - n3) / 3, a1 = (c0 + vhi - 1 - n3) / 3;   // first and last node
+        const double ps = xs * pscale;
+        for (int An = a0 + threadIdx.x; An <= a1; An += blockDim.x) {
+          double s[3];
+          gather_node(sm, F, An, s);
+          double w[3], v0[3];
+          bool own[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int d = 3 * An + c;
+            const int i = n3 + d - c0;
+            own[c] = i >= uhi && i < vhi;
+            w[c] = own[c] ? f * (-M.mih[d] * s[c] + ps * M.p0bar[d]) : 0.0;
+            v0[c] = own[c] ? W.V[c0 + i] : 0.0;
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (own[c]) {
+              const int i = n3 + 3 * An + c - c0;
+              lw[i] = w[c];
+              if (!lvV) lv[i] = v0[c];
+              part += w[c] * v0[c];
+            }
         }
       }
     }
@@ -500,29 +549,59 @@ __device__ ProjResult project_cwy(Team& tm, const ExpvArgs& A, double f, double 
     // w = f A v_{j-1} on the own slice
     const double xs = src[2 * n3] * hinv * M.s_inv;
     const SlotMap sm = slot_map(M);
-    for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
-      double w[LB];
+    if constexpr (SCH == 4) {
+      for (int i0 = threadIdx.x; i0 < nloc; i0 += LB * blockDim.x) {
+        double w[LB];
 #pragma unroll
-      for (int u = 0; u < LB; ++u) {
-        const int i = i0 + u * blockDim.x;
-        w[u] = 0.0;
-        if (i < nloc) {
-          const int g = c0 + i;
-          if constexpr (SCH == 4) {
-            w[u] = m4_entry<T, MODEL>(M, sm, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, g);
-          } else if (g < n3) {
-            w[u] = f * (src[n3 + g] * hinv);
-          } else if (g < 2 * n3) {
-            const int d = g - n3;
-            const double s = gather_slots(sm, F, d / 3, d - (d / 3) * 3);
-            w[u] = f * (-M.mih[d] * s + xs * pscale * M.p0bar[d]);
+        for (int u = 0; u < LB; ++u) {
+          const int i = i0 + u * blockDim.x;
+          w[u] = i < nloc ? m4_entry<T, MODEL>(M, sm, A.op, F, F2, src, hinv, xs, pscale, pscale2, f, c0 + i) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int i = i0 + u * blockDim.x;
+          if (i < nloc) lw[i] = w[u];
+        }
+      }
+    } else {
+      // as in the sequential form: u-part entries one by one, the v-part node by node
+      const int uhi = min(nloc, max(0, n3 - c0));
+      const int vhi = min(nloc, max(uhi, 2 * n3 - c0));
+      for (int r = 0; r < 2; ++r) {
+        const int lo = r == 0 ? 0 : vhi, hi = r == 0 ? uhi : nloc;
+        for (int i0 = lo + threadIdx.x; i0 < hi; i0 += LB * blockDim.x) {
+          double w[LB];
+#pragma unroll
+          for (int u = 0; u < LB; ++u) {
+            const int i = i0 + u * blockDim.x;
+            w[u] = (i < hi && r == 0) ? f * (src[n3 + c0 + i] * hinv) : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < LB; ++u) {
+            const int i = i0 + u * blockDim.x;
+            if (i < hi) lw[i] = w[u];
           }
         }
       }
+      if (uhi < vhi) {
+        const int a0 = (c0 + uhi - n3) / 3, a1 = (c0 + vhi - 1 - n3) / 3;
+        const double ps = xs * pscale;
+        for (int An = a0 + threadIdx.x; An <= a1; An += blockDim.x) {
+          double s[3];
+          gather_node(sm, F, An, s);
+          double w[3];
+          bool own[3];
 #pragma unroll
-      for (int u = 0; u < LB; ++u) {
-        const int i = i0 + u * blockDim.x;
-        if (i < nloc) lw[i] = w[u];
+          for (int c = 0; c < 3; ++c) {
+            const int d = 3 * An + c;
+            const int i = n3 + d - c0;
+            own[c] = i >= uhi && i < vhi;
+            w[c] = own[c] ? f * (-M.mih[d] * s[c] + ps * M.p0bar[d]) : 0.0;
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if (own[c]) lw[n3 + 3 * An + c - c0] = w[c];
+        }
       }
     }
     __syncthreads();
