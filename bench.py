@@ -61,6 +61,8 @@ def parse():
                     help="Arnoldi steps between a-priori error checks in the adaptive runs")
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed_f32", "mixed_bf16"])
     ap.add_argument("--workgroups", type=int, default=0)
+    ap.add_argument("--autotune-steps", type=int, default=5,
+                    help="steps over which the plan autotuner times each candidate plan")
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="keep one workgroup per batch instance (no plan autotuning)")
     ap.add_argument("--ortho", type=int, default=-1, choices=[-1, 0, 1],
@@ -347,7 +349,7 @@ def run_batch(probs, precision, steps, warmup, m_max, stream, torch, args):
     if not getattr(args, "no_batch_autotune", False):
         # the project's plan autotuner: teams of workgroups for the costly blocks, lists of
         # cheap ones (states restored afterwards)
-        wg, tuned_ms = b.autotune(dt, steps=5)
+        wg, tuned_ms = b.autotune(dt, steps=getattr(args, "autotune_steps", 5))
         teams = [b.plan_of(i)[0] for i in range(len(probs))]
         plan = {"workgroups": wg, "max_team": max(teams), "instances_in_teams": sum(g > 1 for g in teams),
                 "autotune_ms_per_step": tuned_ms}
