@@ -381,9 +381,9 @@ ep_status ep_batch_get_stats(ep_ctx* ctx, int32_t instance_id, int64_t* matvecs,
  * rounding level (reductions in another order).
  * ep_batch_autotune times `steps` steps of dt (after one untimed step) for the one-
  * workgroup-per-instance plan, which measures the costs, and for the plans of serial
- * fractions 0.2, 0.35, 0.5 and 0.65; then re-measures the costs under the fastest plan so far
- * (team times converted back through the model) and times the four plans of those costs;
- * each run starts from the same states.  Keeps the fastest plan and restores the states
+ * fractions 0.1, 0.2, 0.3, 0.4, 0.5 and 0.65; then, twice, re-measures the costs under the
+ * fastest plan so far (team times converted back through the model) and times the six plans
+ * of those costs; each run starts from the same states.  Keeps the fastest plan and restores the states
  * (checkpoints), so the trajectory is where it was; outputs the workgroups per launch and
  * the time per step of the kept plan (either may be NULL).  On a failure (a device error in
  * a timing run) it returns that error after putting back one workgroup per instance and

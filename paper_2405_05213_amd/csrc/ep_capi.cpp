@@ -1948,12 +1948,12 @@ ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, do
     }
     s = batch_capacity(c, &cap);
     if (s != EP_OK) break;
-    // two rounds: the plans of the plain plan's costs, then of the costs measured under the
-    // best of them (a fuller machine slows every instance down; a team's time is converted
-    // back to one workgroup's through the same model)
+    // three rounds: the plans of the plain plan's costs, then twice those of the costs
+    // measured under the best plan so far (a fuller machine slows every instance down; a
+    // team's time is converted back to one workgroup's through the same model)
     double best_sf = -1.0;
-    for (int round = 0; round < 2 && s == EP_OK; ++round) {
-      if (round == 1) {
+    for (int round = 0; round < 3 && s == EP_OK; ++round) {
+      if (round >= 1) {
         if (best_sf < 0.0) break;
         s = apply_batch_plan(c, bestG, bestBins);
         if (s != EP_OK) break;
@@ -1973,7 +1973,7 @@ ep_status ep_batch_autotune(ep_ctx* c, double dt, int steps, int* workgroups, do
           cost[i] = t / (best_sf + (1.0 - best_sf) / g);
         }
       }
-      for (double sf : {0.2, 0.35, 0.5, 0.65}) {
+      for (double sf : {0.1, 0.2, 0.3, 0.4, 0.5, 0.65}) {
         make_batch_plan(c, cost, cap, sf, G, bins);
         s = apply_batch_plan(c, G, bins);
         if (s != EP_OK) break;
